@@ -1,0 +1,414 @@
+"""Pins of the FP64 CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every check is against a
+library routine (numpy.fft), a naive sum, a closed form (laminate, single
+Fourier mode, homogeneous cell), an independent direct solve of the discrete
+problem (Galerkin over an explicit compatible basis), an alternative
+derivation (acoustic-tensor Green operator) or an exact invariant (symmetry,
+Loewner bounds, projector identities, affine structure of F).
+"""
+import numpy as np
+import pytest
+
+import closed_forms as CF
+import oracle as O
+from paper_2003_07720_amd import microstructure as M
+
+RNG = np.random.default_rng(12345)
+
+
+# ---------------------------------------------------------------- transforms
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 32, 48, 64, 96, 128])
+def test_fft1_matches_numpy_and_naive(n):
+    x = RNG.standard_normal(n) + 1j * RNG.standard_normal(n)
+    ref = np.fft.fft(x)
+    scale = max(1.0, np.abs(ref).max())
+    assert np.abs(O.fft1(x, -1) - ref).max() <= 1e-13 * scale * np.log2(n + 1)
+    assert np.abs(O.dft_naive(x, -1) - ref).max() <= 1e-13 * scale * n
+    # inverse kernel exp(+...) without 1/n
+    assert np.abs(O.fft1(x, +1) - n * np.fft.ifft(x)).max() <= 1e-13 * scale * np.log2(n + 1)
+
+
+def test_fft3_matches_numpy_and_parseval():
+    a = RNG.standard_normal((6, 4, 12)) + 1j * RNG.standard_normal((6, 4, 12))
+    A = O.fft3(a, -1)
+    assert np.abs(A - np.fft.fftn(a)).max() < 1e-12
+    assert abs((np.abs(A) ** 2).sum() - a.size * (np.abs(a) ** 2).sum()) < 1e-10 * (np.abs(A) ** 2).sum()
+    back = O.fft3(A, +1) / a.size
+    assert np.abs(back - a).max() < 1e-14 * 10
+
+
+# ---------------------------------------------------------------- wave vectors
+
+@pytest.mark.parametrize("n", [(4, 4, 1), (6, 4, 2), (4, 6, 8), (3, 5, 2)])
+def test_wavevector_hermitian_and_matches_rule(n):
+    nx, ny, nz = n
+    for mz in range(nz):
+        for my in range(ny):
+            for mx in range(nx):
+                k = O.wavevector(n, (mx, my, mz))
+                np.testing.assert_allclose(k, CF.wavevector(n, (mx, my, mz)), atol=0)
+                kn = O.wavevector(n, ((-mx) % nx, (-my) % ny, (-mz) % nz))
+                self_conj = all(((-m) % nn) == m for m, nn in zip((mx, my, mz), n))
+                if not self_conj:
+                    np.testing.assert_allclose(kn, -k, atol=0)
+
+
+def test_wavevector_examples():
+    pi = np.pi
+    np.testing.assert_allclose(O.wavevector((4, 4, 1), (2, 1, 0)), [-pi, pi / 2, 0])
+    np.testing.assert_allclose(O.wavevector((4, 4, 1), (2, 3, 0)), [pi, -pi / 2, 0])
+    np.testing.assert_allclose(O.wavevector((4, 4, 1), (2, 0, 0)), [-pi, 0, 0])
+    np.testing.assert_allclose(O.wavevector((4, 4, 4), (1, 2, 3)), [pi / 2, pi, -pi / 2])
+    np.testing.assert_allclose(O.wavevector((8, 4, 2), (3, 0, 0)), [2 * pi * 3 / 8, 0, 0])
+
+
+# ---------------------------------------------------------------- Green operator
+
+def _rand_sym_c():
+    return RNG.standard_normal(6) + 1j * RNG.standard_normal(6)
+
+
+def _frob(a, b):
+    w = np.array([1, 1, 1, 2, 2, 2])
+    return np.sum(w * a * b)
+
+
+def _c0_apply(lame0, e6):
+    lam, mu = lame0
+    tr = e6[0] + e6[1] + e6[2]
+    out = 2 * mu * e6
+    out[:3] += lam * tr
+    return out
+
+
+@pytest.mark.parametrize("trial", range(8))
+def test_green_matches_acoustic_tensor_form(trial):
+    k = RNG.standard_normal(3)
+    lame0 = (RNG.uniform(0.1, 3.0), RNG.uniform(0.1, 3.0))
+    s = _rand_sym_c()
+    np.testing.assert_allclose(O.gamma_apply(k, lame0, s), CF.acoustic_green_apply(k, lame0, s), rtol=0,
+                               atol=1e-14 * np.abs(s).max() / lame0[1] * 10)
+
+
+def test_green_identities():
+    lame0 = CF.lame(3.0, 0.25)
+    for _ in range(10):
+        k = RNG.standard_normal(3)
+        s = _rand_sym_c()
+        t = _rand_sym_c()
+        g = O.gamma_apply(k, lame0, s)
+        # projector: Gamma C0 Gamma = Gamma
+        np.testing.assert_allclose(O.gamma_apply(k, lame0, _c0_apply(lame0, g)), g, atol=1e-13)
+        # Gamma C0 sym(k (x) a) = sym(k (x) a)
+        a = RNG.standard_normal(3)
+        ska = CF.comps_of(0.5 * (np.outer(k, a) + np.outer(a, k)))
+        np.testing.assert_allclose(O.gamma_apply(k, lame0, _c0_apply(lame0, ska)), ska, atol=1e-13)
+        # even, degree-zero homogeneous
+        np.testing.assert_allclose(O.gamma_apply(-k, lame0, s), g, atol=1e-14)
+        np.testing.assert_allclose(O.gamma_apply(7.3 * k, lame0, s), g, atol=1e-13)
+        # major symmetry in the Frobenius product
+        assert abs(_frob(t, g) - _frob(O.gamma_apply(k, lame0, t), s)) < 1e-12
+        # kernel: stresses with sigma.n = 0 map to 0
+        n = k / np.linalg.norm(k)
+        P = np.eye(3) - np.outer(n, n)
+        S = P @ CF.tensor_of(s.real) @ P
+        np.testing.assert_allclose(O.gamma_apply(k, lame0, CF.comps_of(S).astype(complex)), 0, atol=1e-14)
+    np.testing.assert_allclose(O.gamma_apply(np.zeros(3), lame0, _rand_sym_c()), 0, atol=0)
+
+
+# ---------------------------------------------------------------- the map F
+
+def test_error_single_mode_closed_form():
+    """sigma = S0 + S1 cos(2 pi m.x/n) in a homogeneous cell: the equilibrium error is
+    |k S1| / (sqrt 2 |S0|) with the Frobenius norm."""
+    n = (8, 6, 4)
+    lt = np.array([CF.lame(2.0, 0.3)])
+    lam, mu = lt[0]
+    S0 = CF.tensor_of(RNG.standard_normal(6))
+    S1 = CF.tensor_of(RNG.standard_normal(6))
+    m = (1, 2, 1)
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    cosf = np.cos(2 * np.pi * (m[0] * x / n[0] + m[1] * y / n[1] + m[2] * z / n[2]))
+    sig = CF.comps_of(S0)[:, None, None, None] + CF.comps_of(S1)[:, None, None, None] * cosf[None]
+    # eps = C^-1 sigma (isotropic compliance)
+    tr = sig[0] + sig[1] + sig[2]
+    eps = (sig - (lam / (3 * lam + 2 * mu)) * np.array([tr, tr, tr, 0 * tr, 0 * tr, 0 * tr])) / (2 * mu)
+    ph = np.zeros((n[2], n[1], n[0]), np.uint8)
+    _, err, sav, _ = O.fmap(ph, lt, CF.lame(2.0, 0.3), np.zeros(6), eps)
+    k = CF.wavevector(n, m)
+    expect = np.linalg.norm(S1 @ k) / (np.sqrt(2) * np.linalg.norm(S0))
+    assert abs(err - expect) < 1e-13 * expect
+    np.testing.assert_allclose(sav, CF.comps_of(S0), atol=1e-14)
+
+
+def test_error_inplane_norm_2d():
+    """In 2-D (nz = 1) the normalisation uses the in-plane part of <sigma> only."""
+    n = (8, 8, 1)
+    lt = np.array([CF.lame(1.0, 0.3)])
+    eps = np.zeros((6, 1, 8, 8))
+    x = np.arange(8)
+    eps[0] = 1e-3 + 1e-4 * np.sin(2 * np.pi * x / 8)[None, None, :]
+    ph = np.zeros((1, 8, 8), np.uint8)
+    _, err, sav, _ = O.fmap(ph, lt, CF.lame(1.0, 0.3), np.zeros(6), eps)
+    lam, mu = lt[0]
+    S0 = np.array([[lam * 1e-3 + 2 * mu * 1e-3, 0], [0, lam * 1e-3]])
+    k = 2 * np.pi / 8
+    amp = (lam + 2 * mu) * 1e-4  # sigma_xx amplitude of the sine mode
+    expect = k * amp / np.sqrt(2) / np.linalg.norm(S0)
+    assert abs(err - expect) < 1e-12 * expect
+    assert abs(sav[2] - lam * 1e-3) < 1e-15  # sigma_zz reported, plane strain
+
+
+def test_homogeneous_one_step():
+    ph = np.zeros((4, 6, 8), np.uint8)
+    lt = np.array([CF.lame(1.7, 0.31)])
+    E = RNG.standard_normal(6) * 1e-2
+    r = O.solve(ph, lt, CF.lame(5.0, 0.2), E, scheme="rpm", tol=1e-10)
+    assert r["status"] == "converged" and r["iterations"] == 1
+    assert r["residual"] < 1e-14
+    np.testing.assert_allclose(r["eps"], np.broadcast_to(E[:, None, None, None], r["eps"].shape), atol=0)
+
+
+def test_fmap_real_output_on_even_grids():
+    """The Hermitian-consistent Nyquist wave vector leaves no imaginary part."""
+    ph = M.random_phases((4, 6, 8), 3, seed=1)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(7, 0.2), CF.lame(0.1, 0.45)])
+    eps = M.random_field((4, 6, 8), seed=2)
+    _, _, _, im = O.fmap(ph, lt, CF.lame(4, 0.3), np.zeros(6), eps)
+    assert im < 1e-14
+
+
+def test_fmap_affine_structure():
+    """F(u + v) - F(u) = F(v; E = 0) (F is affine; used for the exact JVP)."""
+    shape = (2, 6, 4)
+    ph = M.random_phases(shape, 2, seed=3)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(20, 0.25)])
+    l0 = CF.lame(10, 0.3)
+    E = RNG.standard_normal(6)
+    u = M.random_field(shape, seed=4)
+    v = M.random_field(shape, seed=5)
+    fu = O.fmap(ph, lt, l0, E, u)[0]
+    fuv = O.fmap(ph, lt, l0, E, u + v)[0]
+    fv = O.fmap(ph, lt, l0, np.zeros(6), v)[0]
+    np.testing.assert_allclose(fuv - fu, fv, atol=1e-12)
+
+
+def test_fmap_fixed_point_is_equilibrium():
+    """At the Galerkin (exact discrete) solution, F returns its input and the error vanishes."""
+    shape = (4, 4, 4)
+    ph = M.random_phases(shape, 2, seed=6)
+    tab = [(1.0, 0.3), (5.0, 0.2)]
+    lt = CF.np.array([CF.lame(*p) for p in tab])
+    E = np.array([0.01, -0.002, 0.003, 0.001, 0.0, 0.004])
+    eps, _ = CF.galerkin_solution(ph, lt, E)
+    xi, err, _, _ = O.fmap(ph, lt, CF.lame(3.0, 0.3), E, eps)
+    assert err < 1e-12
+    np.testing.assert_allclose(xi, eps, atol=1e-14)
+
+
+# ---------------------------------------------------------------- exact solutions
+
+@pytest.mark.parametrize("axis,shape,layers", [
+    (2, (4, 4, 8), [0, 0, 1, 1, 1, 0, 2, 0]),
+    (0, (12, 2, 2), [1, 0, 0, 2, 2, 2, 0, 1, 1, 0, 0, 0]),
+    (1, (1, 6, 1), [0, 1, 0, 0, 1, 2]),  # 2-D, single-voxel layers
+])
+@pytest.mark.parametrize("scheme", ["basic", "rpm"])
+def test_laminate_exact(axis, shape, layers, scheme):
+    nx, ny, nz = shape
+    if axis == 1:
+        shape = (4, 6, 1)
+        nx, ny, nz = shape
+    ph = M.laminate(shape, layers, axis=axis)
+    tab = [(1.0, 0.3), (8.0, 0.25), (3.0, 0.35)]
+    lt = np.array([CF.lame(*p) for p in tab])
+    E = np.array([0.01, 0.002, -0.003, 0.004, -0.001, 0.002])
+    if nz == 1:
+        E[2] = E[3] = E[4] = 0.0
+    ref_eps, ref_sig = CF.laminate_solution(ph, lt, E, axis)
+    r = O.solve(ph, lt, CF.lame(5.0, 0.3), E, scheme=scheme, tol=1e-13, max_iter=5000)
+    assert r["status"] == "converged"
+    np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-13 * 10)
+    np.testing.assert_allclose(r["sig_avg"], ref_sig, atol=1e-13 * 10)
+
+
+@pytest.mark.parametrize("shape,n_ph,seed", [((1, 8, 8), 2, 11), ((4, 4, 4), 2, 12), ((2, 4, 6), 3, 13)])
+def test_galerkin_direct_solve(shape, n_ph, seed):
+    ph = M.random_phases(shape, n_ph, seed=seed)
+    tab = [(1.0, 0.3), (6.0, 0.25), (0.5, 0.4)][:n_ph]
+    lt = np.array([CF.lame(*p) for p in tab])
+    E = np.array([0.01, -0.004, 0.002, 0.003, -0.002, 0.005])
+    if shape[0] == 1:
+        E[2] = E[3] = E[4] = 0.0
+    ref_eps, ref_sig = CF.galerkin_solution(ph, lt, E)
+    for scheme in ("basic", "rpm"):
+        r = O.solve(ph, lt, CF.lame(4.0, 0.3), E, scheme=scheme, tol=1e-13, max_iter=20000, n_max=5)
+        assert r["status"] == "converged", (scheme, r["status"], r["residual"])
+        np.testing.assert_allclose(r["eps"], ref_eps, atol=2e-13)
+        np.testing.assert_allclose(r["sig_avg"], ref_sig, atol=2e-13)
+
+
+@pytest.mark.slow
+def test_disk32_matches_galerkin():
+    """The 2-D 32 x 32 disk workload: basic and RPM at 1e-8 agree with the direct solve."""
+    w = M.workload_disk32()
+    lt = O.lame_table(w["phases"])
+    ref_eps, ref_sig = CF.galerkin_solution(w["phase"], lt, w["E"])
+    for scheme in ("basic", "rpm"):
+        r = O.solve(w["phase"], lt, O.lame(*w["ref"]), w["E"], scheme=scheme, tol=1e-12, max_iter=5000)
+        assert r["status"] == "converged"
+        np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
+        np.testing.assert_allclose(r["sig_avg"], ref_sig, rtol=1e-11, atol=1e-16)
+        r8 = O.solve(w["phase"], lt, O.lame(*w["ref"]), w["E"], scheme=scheme, tol=1e-8)
+        assert r8["status"] == "converged"
+        # error 1e-8 bounds the distance to the exact solution (contrast 10)
+        assert np.abs(r8["eps"] - ref_eps).max() < 1e-6 * 0.01 * 10
+
+
+# ---------------------------------------------------------------- effective tensor
+
+def test_effective_tensor_symmetry_and_bounds_3d():
+    shape = (6, 6, 6)
+    ph = M.random_phases(shape, 2, seed=21)
+    tab = [(1.0, 0.3), (10.0, 0.25)]
+    lt = np.array([CF.lame(*p) for p in tab])
+    C, runs = O.effective_tensor(ph, lt, CF.lame(5.5, 0.3), scheme="rpm", tol=1e-12, max_iter=3000)
+    assert all(r["status"] == "converged" for r in runs)
+    np.testing.assert_allclose(C, C.T, atol=1e-10 * np.abs(C).max())
+    Cm = CF.voigt_to_mandel(C)
+    assert np.linalg.eigvalsh(CF.voigt_bound(ph, lt) - Cm).min() > -1e-10
+    assert np.linalg.eigvalsh(Cm - CF.reuss_bound(ph, lt)).min() > -1e-10
+    # the basis carried over from earlier load cases is reused (F_u does not depend on E)
+    assert runs[-1]["basis"].p >= runs[0]["p"]
+
+
+def test_effective_tensor_2d_bounds():
+    ph = M.random_phases((1, 8, 8), 2, seed=22)
+    tab = [(1.0, 0.3), (10.0, 0.3)]
+    lt = np.array([CF.lame(*p) for p in tab])
+    C, runs = O.effective_tensor(ph, lt, CF.lame(5.5, 0.3), scheme="basic", tol=1e-12, max_iter=3000)
+    assert C.shape == (3, 3)
+    np.testing.assert_allclose(C, C.T, atol=1e-10 * np.abs(C).max())
+    Cm = CF.voigt_to_mandel(C)
+    assert np.linalg.eigvalsh(CF.voigt_bound(ph, lt, two_d=True) - Cm).min() > -1e-10
+    assert np.linalg.eigvalsh(Cm - CF.reuss_bound(ph, lt, two_d=True)).min() > -1e-10
+
+
+def test_laminate_effective_tensor_exact():
+    """Every column of the effective tensor of a laminate equals the closed form."""
+    shape = (2, 2, 8)
+    ph = M.laminate(shape, [0, 1, 1, 0, 0, 0, 1, 0], axis=2)
+    lt = np.array([CF.lame(1.0, 0.3), CF.lame(4.0, 0.2)])
+    C, _ = O.effective_tensor(ph, lt, CF.lame(3.0, 0.3), scheme="rpm", tol=1e-13, max_iter=3000)
+    for j in range(6):
+        _, sig = CF.laminate_solution(ph, lt, O.unit_load(j), axis=2)
+        np.testing.assert_allclose(C[:, j], sig, atol=1e-12)
+
+
+# ---------------------------------------------------------------- RPM invariants
+
+def test_rpm_without_basis_is_basic_bitwise():
+    shape = (4, 4, 4)
+    ph = M.random_phases(shape, 2, seed=31)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(30, 0.3)])
+    E = np.array([0.01, 0, 0, 0, 0, 0.002])
+    rb = O.solve(ph, lt, CF.lame(15.5, 0.3), E, scheme="basic", tol=1e-10, max_iter=60)
+    rr = O.solve(ph, lt, CF.lame(15.5, 0.3), E, scheme="rpm", p_max=0, tol=1e-10, max_iter=60)
+    assert rb["iterations"] == rr["iterations"]
+    assert np.array_equal(rb["eps"], rr["eps"])
+    assert np.array_equal(rb["history"], rr["history"])
+
+
+def test_rpm_basis_invariants_and_same_fixed_point():
+    shape = (1, 16, 16)
+    ph = M.disk_2d(16, 0.3)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(100, 0.3)])
+    E = np.array([0, 0, 0, 0, 0, 0.005])
+    l0 = CF.lame(50.5, 0.3)
+    rr = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-11, max_iter=4000, n_max=6)
+    rb = O.solve(ph, lt, l0, E, scheme="basic", tol=1e-11, max_iter=20000)
+    assert rr["status"] == "converged" and rb["status"] == "converged"
+    assert rr["iterations"] < rb["iterations"]  # RPM stabilises the slow modes (contrast 100)
+    np.testing.assert_allclose(rr["eps"], rb["eps"], atol=1e-9 * 0.005 * 100)
+    b = rr["basis"]
+    p = b.p
+    assert p >= 1
+    Z = b.Z[:p].reshape(p, 6, -1)
+    w = np.array([1, 1, 1, 2, 2, 2])[None, :, None]
+    G = np.einsum("acx,bcx->ab", Z * w, Z)
+    np.testing.assert_allclose(G, np.eye(p), atol=1e-12)
+    W = b.W[:p].reshape(p, 6, -1)
+    np.testing.assert_allclose(b.H[:p, :p], np.einsum("acx,bcx->ab", Z * w, W), atol=1e-12)
+    # W columns are exact JVPs
+    for j in range(p):
+        fz = O.fmap(ph, lt, l0, np.zeros(6), Z[j].reshape(6, *shape))[0]
+        np.testing.assert_allclose(fz.reshape(6, -1), W[j], atol=1e-13)
+
+
+def test_rpm_complete_basis_one_newton_step():
+    """With Z spanning the whole compatible space, one Newton step lands on the solution."""
+    shape = (1, 4, 4)
+    ph = M.random_phases(shape, 2, seed=41)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(1000, 0.3)])
+    l0 = CF.lame(2.0, 0.3)  # the plain fixed point diverges here (E0 < E_max / 2)
+    E = np.array([0.01, 0.003, 0, 0, 0, -0.002])
+    V = CF.compatible_basis(shape)  # Mandel, orthonormal
+    Zt = (V.reshape(6, -1, V.shape[1]) / CF.MANDEL_W[:, None, None])  # tensor components
+    p = V.shape[1]
+    basis = O.Basis(shape, p)
+    for j in range(p):
+        basis.Z[j] = Zt[:, :, j].ravel()
+        basis.W[j] = O.fmap(ph, lt, l0, np.zeros(6), Zt[:, :, j].reshape(6, *shape))[0].ravel()
+    w = np.repeat(np.array([1, 1, 1, 2, 2, 2.0]), 16)
+    basis.H[:p, :p] = (basis.Z[:p] * w) @ basis.W[:p].T
+    basis.p = p
+    r = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-11, max_iter=10, p_max=p, basis=basis)
+    assert r["status"] == "converged" and r["iterations"] == 2
+    ref_eps, _ = CF.galerkin_solution(ph, lt, E)
+    np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
+
+
+def test_basic_diverges_below_half_max_modulus():
+    """Classical scheme: spectrum of F_u in [1 - E_max/E0, 1 - E_min/E0] (equal nu); a
+    reference modulus below E_max / 2 puts an eigenvalue below -1 and the iteration
+    diverges, which the oracle reports."""
+    ph = M.random_phases((4, 4, 4), 2, seed=51)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(100, 0.3)])
+    r = O.solve(ph, lt, CF.lame(30.0, 0.3), np.array([0.01, 0, 0, 0, 0, 0]), scheme="basic", tol=1e-8,
+                max_iter=5000)
+    assert r["status"] == "diverged"
+
+
+def test_replay_forces_growth_decisions():
+    ph = M.disk_2d(16, 0.3)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(100, 0.3)])
+    E = np.array([0.01, 0, 0, 0, 0, 0])
+    l0 = CF.lame(50.5, 0.3)
+    free = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-10, max_iter=200, n_max=4)
+    forced = [1] * len(free["decisions"])
+    rr = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-10, max_iter=200, n_max=4, replay=forced)
+    assert list(rr["decisions"][:len(forced)]) == forced
+    again = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-10, max_iter=200, n_max=4,
+                    replay=list(free["decisions"]))
+    assert np.array_equal(again["eps"], free["eps"])
+
+
+def test_compatible_projection():
+    """Gamma0 C0 keeps compatible zero-mean fields, kills uniform fields and is idempotent."""
+    shape = (2, 4, 6)
+    l0 = CF.lame(2.0, 0.3)
+    V = CF.compatible_basis(shape)
+    coef = RNG.standard_normal(V.shape[1])
+    f = (V @ coef).reshape(6, -1) / CF.MANDEL_W[:, None]
+    f = f.reshape((6,) + shape)
+    np.testing.assert_allclose(O.project_compatible(f, l0), f, atol=1e-13)
+    u = np.broadcast_to(RNG.standard_normal(6)[:, None, None, None], (6,) + shape).copy()
+    np.testing.assert_allclose(O.project_compatible(u, l0), 0, atol=1e-15)
+    g = M.random_field(shape, seed=61)
+    pg = O.project_compatible(g, l0)
+    np.testing.assert_allclose(O.project_compatible(pg, l0), pg, atol=1e-13)
+    # the result lies in the span of the explicit compatible basis
+    pm = (pg.reshape(6, -1) * CF.MANDEL_W[:, None]).ravel()
+    np.testing.assert_allclose(V @ (V.T @ pm), pm, atol=1e-12)
