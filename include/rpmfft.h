@@ -1,0 +1,185 @@
+/*
+ * rpmfft.h -- C ABI of the MI355X (gfx950) RPM-FFT solver.
+ *
+ * The solver computes the strain and stress fields in a periodic cell of a
+ * heterogeneous linear-elastic solid for a prescribed mean strain, and the
+ * effective stiffness, following Peng, Nepal & Dayal, "Effective Response of
+ * Heterogeneous Materials using the Recursive Projection Method", CMAME 364
+ * (2020):
+ *   - the cell problem and the mean/fluctuation split of Sec. 2;
+ *   - the Lippmann-Schwinger fixed-point map of Algorithm 1 and the operator
+ *     F of Sec. 3 (stress C(x):eps, forward FFT, reference-medium Green
+ *     operator at every non-zero frequency, mean strain at k = 0, inverse
+ *     FFT), with the equilibrium error of Algorithm 1;
+ *   - the Recursive Projection Method of Sec. 3 / Algorithm 2 around it
+ *     (projection on the basis Z, Newton on the unstable subspace with
+ *     H = Z^T F_u Z, fixed point on the complement, basis growth In(q, Z)).
+ *
+ * Conventions
+ *   - Grid n = {nx, ny, nz}; nz == 1 is 2-D plane strain.  Every extent is a
+ *     product of 2s and 3s between 2 and 512 (nz may also be 1).
+ *   - Fields are real arrays [6][nz][ny][nx] (x fastest) in the working
+ *     precision (double for RPM_FP64, float for RPM_FP32), tensor components
+ *     in the order xx, yy, zz, yz, xz, xy with tensor (not engineering)
+ *     shear.  The mean strain E[6] uses the same components.
+ *   - The phase map is uint8 [nz][ny][nx]; phase p has Lame constants
+ *     lame[2p], lame[2p+1] (lambda, mu).  The reference medium is isotropic
+ *     (lambda0, mu0).
+ *   - The equilibrium error is sqrt(<|div sigma|^2>)/|<sigma>| with the
+ *     divergence in voxel units (wave vectors in radians per voxel) and the
+ *     Frobenius norm; in 2-D the norm of <sigma> uses the in-plane part.
+ *   - Inner products between fields (projections, Gram-Schmidt) are
+ *     Frobenius sums over voxels.
+ *
+ * Memory and ownership
+ *   - Pointers documented as DEVICE point to GPU memory the caller owns
+ *     (e.g. torch tensors); HOST pointers to host memory.  The library never
+ *     allocates device memory: all scratch lives in the caller's workspace,
+ *     sized by rpm_workspace_size.  The workspace also carries state between
+ *     calls (the basis Z, W = F_u Z and H), so consecutive solves on the same
+ *     workspace can reuse the basis (F_u does not depend on E).
+ *   - All device work is enqueued on the caller's HIP stream (NULL = the
+ *     default stream); every entry point returns after that work completed.
+ *   - Calls on different workspaces are independent; calls that share a
+ *     workspace must not overlap.
+ *
+ * Errors
+ *   - Negative codes are returned before any device work and leave outputs
+ *     untouched.  RPM_NOT_CONVERGED, RPM_DIVERGED and RPM_SINGULAR fill the
+ *     outputs from the last iterate and the statistics.
+ */
+#ifndef RPMFFT_H
+#define RPMFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RPM_OK = 0,                 /* error <= tol                                  */
+    RPM_NOT_CONVERGED = 1,      /* max_iter main-loop F applications reached     */
+    RPM_DIVERGED = 2,           /* non-finite error or error > 1e6 x initial     */
+    RPM_SINGULAR = 3,           /* I - H has a pivot below 1e-14 max|I - H|      */
+    RPM_E_INVALID = -1,         /* bad argument (null pointer, range, NaN ...)   */
+    RPM_E_UNSUPPORTED_SIZE = -2,/* an extent is not a 2,3-smooth size <= 512     */
+    RPM_E_WORKSPACE = -3,       /* workspace missing or smaller than required    */
+    RPM_E_HIP = -5              /* a HIP runtime call failed                     */
+} rpm_status;
+
+enum { RPM_SCHEME_BASIC = 0, /* Algorithm 1: eps <- F(eps)                       */
+       RPM_SCHEME_RPM = 1 }; /* Algorithm 2                                      */
+
+enum { RPM_FP64 = 0,         /* fields, FFTs and Z in double                     */
+       RPM_FP32 = 1 };       /* fields, FFTs and Z in float; reductions, norms,
+                                Gram-Schmidt coefficients, H and the Newton
+                                solve in double                                   */
+
+enum { RPM_K_XFWD = 0, RPM_K_YFWD, RPM_K_GAMMA, RPM_K_YINV, RPM_K_XINV, RPM_K_REDUCE, RPM_K_FINAL,
+       RPM_K_GROWTH, RPM_NKERNEL };
+
+typedef struct {
+    int32_t n[3];             /* nx, ny, nz                                      */
+    const uint8_t *phase;     /* DEVICE [nz][ny][nx] phase labels                */
+    int32_t n_phases;         /* 1..256                                          */
+    const double *lame;       /* HOST [n_phases][2] (lambda, mu), mu >= 0,
+                                 3 lambda + 2 mu >= 0                            */
+    double lame0[2];          /* reference medium (lambda0, mu0), mu0 > 0,
+                                 3 lambda0 + 2 mu0 > 0                           */
+} rpm_problem;
+
+typedef struct {
+    double tol;               /* stop when the equilibrium error <= tol (> 0)   */
+    int32_t max_iter;         /* cap on main-loop F applications (>= 1)         */
+    int32_t n_max;            /* fixed-point count before the basis grows (>=1)*/
+    int32_t p_max;            /* basis cap, 0..64 (0 with RPM = Algorithm 1)    */
+    double kappa;             /* add one column when T22 <= kappa T11 (0..1)    */
+    int32_t scheme;           /* RPM_SCHEME_BASIC or RPM_SCHEME_RPM              */
+    int32_t precision;        /* RPM_FP64 or RPM_FP32                            */
+    int32_t reuse_basis;      /* keep Z, W, H left in the workspace by the
+                                 previous call on the same grid and precision   */
+    int32_t check_every;      /* host reads the convergence flag every this many
+                                 iterations (>= 1); iterations queued after
+                                 convergence do nothing                          */
+    const int32_t *replay;    /* HOST, nullable: forced number of columns (0, 1
+                                 or 2) at each growth event, in order            */
+    int32_t replay_len;
+    int32_t profile;          /* record per-kernel-class times with HIP events */
+} rpm_options;
+
+typedef struct {
+    int32_t iterations;       /* main-loop F applications, the initial included */
+    int32_t jvps;             /* F applications for H (one per basis column)     */
+    int32_t basis_dim;        /* p at exit                                       */
+    int32_t growth_events;
+    double residual;          /* equilibrium error of the returned strain        */
+    double seconds;           /* wall time of the call                           */
+    double *history;          /* HOST, nullable: error after each main F call    */
+    int32_t history_cap;
+    int32_t *decisions;       /* HOST, nullable: columns added at each growth    */
+    int32_t decisions_cap;
+    double kernel_ms[RPM_NKERNEL];     /* summed HIP-event times (profile = 1)  */
+    int32_t kernel_launches[RPM_NKERNEL];
+} rpm_stats;
+
+/* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
+ * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16. */
+void rpm_default_options(rpm_options *o);
+
+/* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and
+ * Poisson's ratio nu (nu < 1/2).  Returns RPM_E_INVALID for nu >= 1/2 or
+ * non-finite input. */
+rpm_status rpm_lame_from_young(double E, double nu, double *lam, double *mu);
+
+/* Bytes of device workspace needed for grid n under options o. */
+rpm_status rpm_workspace_size(const int32_t n[3], const rpm_options *o, size_t *bytes);
+
+/*
+ * One application of the fixed-point map (Algorithm 1, lines 5-9):
+ * xi = F(eps; E) and the equilibrium error of eps, <sigma> = <C(x):eps>.
+ * eps, xi: DEVICE fields in o->precision (may not alias).  err, sig_avg: HOST
+ * (nullable).
+ */
+rpm_status rpm_fft_apply(const rpm_problem *pr, const double E[6], const rpm_options *o, const void *eps, void *xi,
+                         double *err, double sig_avg[6], void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * Solve the cell problem for the mean strain E (Sec. 2) with Algorithm 1 or
+ * Algorithm 2 until the equilibrium error of the iterate is <= tol.
+ *   eps0     DEVICE nullable: starting strain (its mean is replaced by E by
+ *            the first application of F); NULL starts from the uniform E.
+ *   eps_out  DEVICE nullable: the iterate whose error met tol (the input of
+ *            the last F application).
+ *   sig_out  DEVICE nullable: C(x):eps_out.
+ *   sig_avg  HOST nullable: <sigma> of eps_out.
+ *   st       HOST nullable: statistics.
+ */
+rpm_status rpm_fft_solve(const rpm_problem *pr, const double E[6], const rpm_options *o, const void *eps0,
+                         void *eps_out, void *sig_out, double sig_avg[6], rpm_stats *st, void *workspace,
+                         size_t ws_bytes, void *hip_stream);
+
+/*
+ * Effective stiffness (the effective response of the title): one solve per
+ * unit mean strain, columns in Voigt order 11, 22, 33, 23, 13, 12 with
+ * engineering shear (a shear load case has eps_ab = eps_ba = 1/2), so that
+ * <sigma> = C_eff gamma.  3-D: C_eff is 6x6 (36 doubles, row major); 2-D
+ * (nz == 1): 3x3 over 11, 22, 12 (9 doubles).  Z, W and H carry over from one
+ * load case to the next when o->reuse_basis is set (F_u does not depend on E).
+ *   C_eff  HOST (36 or 9 doubles);  st  HOST nullable, 6 (or 3) entries.
+ */
+rpm_status rpm_fft_effective_tensor(const rpm_problem *pr, const rpm_options *o, double *C_eff, rpm_stats *st,
+                                    void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Current basis dimension stored in a workspace (0 if never used).  HOST p. */
+rpm_status rpm_workspace_basis_dim(const void *workspace, size_t ws_bytes, int32_t *p, void *hip_stream);
+
+/* Static string naming a status code. */
+const char *rpm_status_string(rpm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPMFFT_H */

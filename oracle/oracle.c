@@ -617,7 +617,7 @@ int orc_solve(int nx, int ny, int nz, const unsigned char *phase, const double *
 
         /* basis growth once nu exceeds n_max (skipped once converged: it
          * cannot change the returned iterate) */
-        if (nu > n_max && p < p_max && err > tol && isfinite(err)) {
+        if (nu > n_max && p < p_max && err > tol && isfinite(err) && err <= 1e6 * err0 && iters < max_iter) {
             int want = 0;
             int ncol = 0;
             if (nq >= 2) {

@@ -1,0 +1,258 @@
+"""ctypes binding of librpmfft.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/rpmfft.h; all
+arithmetic runs in the HIP kernels of the library.  Device buffers are torch
+tensors on the current HIP device (PyTorch provides memory and the stream);
+small arrays are host numpy arrays.  If the library is missing the import
+fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime first so the library shares it
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpmfft.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+RPM_NKERNEL = 8
+KERNEL_NAMES = ["xfwd", "yfwd", "gamma", "yinv", "xinv", "reduce", "finalize", "growth"]
+STATUS = {0: "RPM_OK", 1: "RPM_NOT_CONVERGED", 2: "RPM_DIVERGED", 3: "RPM_SINGULAR", -1: "RPM_E_INVALID",
+          -2: "RPM_E_UNSUPPORTED_SIZE", -3: "RPM_E_WORKSPACE", -5: "RPM_E_HIP"}
+SCHEME = {"basic": 0, "rpm": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+
+
+class RpmProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("phase", ctypes.c_void_p), ("n_phases", ctypes.c_int32),
+                ("lame", ctypes.POINTER(ctypes.c_double)), ("lame0", ctypes.c_double * 2)]
+
+
+class RpmOptions(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("n_max", ctypes.c_int32),
+                ("p_max", ctypes.c_int32), ("kappa", ctypes.c_double), ("scheme", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("reuse_basis", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("replay", ctypes.POINTER(ctypes.c_int32)), ("replay_len", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
+
+
+class RpmStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("jvps", ctypes.c_int32), ("basis_dim", ctypes.c_int32),
+                ("growth_events", ctypes.c_int32), ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
+                ("decisions", ctypes.POINTER(ctypes.c_int32)), ("decisions_cap", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double * RPM_NKERNEL), ("kernel_launches", ctypes.c_int32 * RPM_NKERNEL)]
+
+
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+_dp = _P(ctypes.c_double)
+_lib.rpm_default_options.argtypes = [_P(RpmOptions)]
+_lib.rpm_default_options.restype = None
+_lib.rpm_lame_from_young.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
+_lib.rpm_workspace_size.argtypes = [_P(ctypes.c_int32), _P(RpmOptions), _P(ctypes.c_size_t)]
+_lib.rpm_fft_apply.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _dp, _dp, _vp, ctypes.c_size_t, _vp]
+_lib.rpm_fft_solve.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _vp, _dp, _P(RpmStats), _vp,
+                               ctypes.c_size_t, _vp]
+_lib.rpm_fft_effective_tensor.argtypes = [_P(RpmProblem), _P(RpmOptions), _dp, _P(RpmStats), _vp, ctypes.c_size_t,
+                                          _vp]
+_lib.rpm_workspace_basis_dim.argtypes = [_vp, ctypes.c_size_t, _P(ctypes.c_int32), _vp]
+_lib.rpm_status_string.argtypes = [ctypes.c_int]
+_lib.rpm_status_string.restype = ctypes.c_char_p
+for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve", "rpm_fft_effective_tensor",
+           "rpm_workspace_basis_dim"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve",
+            "rpm_fft_effective_tensor", "rpm_workspace_basis_dim", "rpm_status_string"]
+
+
+class RpmError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {status_string(code)} ({code})")
+        self.code = code
+
+
+def status_string(code):
+    return _lib.rpm_status_string(int(code)).decode()
+
+
+def lame_from_young(E, nu):
+    lam = ctypes.c_double()
+    mu = ctypes.c_double()
+    rc = _lib.rpm_lame_from_young(float(E), float(nu), ctypes.byref(lam), ctypes.byref(mu))
+    if rc != 0:
+        raise RpmError(rc, "rpm_lame_from_young")
+    return lam.value, mu.value
+
+
+def make_options(**kw):
+    o = RpmOptions()
+    _lib.rpm_default_options(ctypes.byref(o))
+    replay = kw.pop("replay", None)
+    for k, v in kw.items():
+        if k == "scheme" and isinstance(v, str):
+            v = SCHEME[v]
+        if k == "precision" and isinstance(v, str):
+            v = PRECISION[v]
+        setattr(o, k, v)
+    keep = None
+    if replay is not None and len(replay) > 0:
+        keep = (ctypes.c_int32 * len(replay))(*[int(x) for x in replay])
+        o.replay = ctypes.cast(keep, _P(ctypes.c_int32))
+        o.replay_len = len(replay)
+    o._keep = keep  # keep the replay array alive with the options
+    return o
+
+
+def field_dtype(opts):
+    return torch.float64 if opts.precision == 0 else torch.float32
+
+
+def _problem(phase, lame_tab, lame0):
+    if not (isinstance(phase, torch.Tensor) and phase.is_cuda and phase.dtype == torch.uint8 and phase.dim() == 3):
+        raise ValueError("phase must be a uint8 device tensor of shape (nz, ny, nx)")
+    if not phase.is_contiguous():
+        raise ValueError("phase must be contiguous")
+    lt = np.ascontiguousarray(np.asarray(lame_tab, dtype=np.float64).reshape(-1, 2))
+    pr = RpmProblem()
+    nz, ny, nx = phase.shape
+    pr.n[0], pr.n[1], pr.n[2] = nx, ny, nz
+    pr.phase = phase.data_ptr()
+    pr.n_phases = lt.shape[0]
+    pr.lame = lt.ctypes.data_as(_dp)
+    pr.lame0[0], pr.lame0[1] = float(lame0[0]), float(lame0[1])
+    pr._keep = lt
+    return pr
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def workspace_size(shape, opts):
+    nz, ny, nx = shape
+    n = (ctypes.c_int32 * 3)(nx, ny, nz)
+    b = ctypes.c_size_t()
+    rc = _lib.rpm_workspace_size(n, ctypes.byref(opts), ctypes.byref(b))
+    if rc != 0:
+        raise RpmError(rc, "rpm_workspace_size")
+    return b.value
+
+
+def make_workspace(shape, opts, device="cuda"):
+    return torch.empty(workspace_size(shape, opts), dtype=torch.uint8, device=device)
+
+
+def _check_field(t, shape, dtype, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor")
+    if tuple(t.shape) != (6,) + tuple(shape):
+        raise ValueError(f"{name} must have shape {(6,) + tuple(shape)}")
+
+
+def fft_apply(phase, lame_tab, lame0, E, eps, opts=None, workspace=None):
+    """xi = F(eps; E) (Algorithm 1, one map application), its error and <sigma>."""
+    opts = opts or make_options()
+    shape = tuple(phase.shape)
+    _check_field(eps, shape, field_dtype(opts), "eps")
+    ws = workspace if workspace is not None else make_workspace(shape, opts)
+    xi = torch.empty_like(eps)
+    pr = _problem(phase, lame_tab, lame0)
+    Ea = (ctypes.c_double * 6)(*[float(x) for x in E])
+    err = ctypes.c_double()
+    sav = (ctypes.c_double * 6)()
+    rc = _lib.rpm_fft_apply(ctypes.byref(pr), Ea, ctypes.byref(opts), eps.data_ptr(), xi.data_ptr(),
+                            ctypes.byref(err), sav, ws.data_ptr(), ws.numel(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fft_apply")
+    return xi, err.value, np.array(sav[:])
+
+
+def _stats_dict(st, hist, dec):
+    it = st.iterations
+    return dict(iterations=it, jvps=st.jvps, basis_dim=st.basis_dim, growth_events=st.growth_events,
+                residual=st.residual, seconds=st.seconds,
+                history=hist[:min(it, hist.size)].copy() if hist is not None else None,
+                decisions=dec[:min(st.growth_events, dec.size)].copy() if dec is not None else None,
+                kernel_ms={KERNEL_NAMES[k]: st.kernel_ms[k] for k in range(RPM_NKERNEL)},
+                kernel_launches={KERNEL_NAMES[k]: st.kernel_launches[k] for k in range(RPM_NKERNEL)})
+
+
+def _new_stats(hist_cap):
+    st = RpmStats()
+    hist = np.zeros(max(hist_cap, 1))
+    dec = np.zeros(4096, dtype=np.int32)
+    st.history = hist.ctypes.data_as(_dp)
+    st.history_cap = hist_cap
+    st.decisions = dec.ctypes.data_as(_P(ctypes.c_int32))
+    st.decisions_cap = dec.size
+    return st, hist, dec
+
+
+def fft_solve(phase, lame_tab, lame0, E, opts=None, eps0=None, workspace=None, want_eps=True, want_sig=False,
+              history_cap=100000, check=True):
+    """Solve for mean strain E (Algorithm 1 or 2).  Returns a dict with status, eps,
+    sig (optional), sig_avg and the statistics."""
+    opts = opts or make_options()
+    shape = tuple(phase.shape)
+    dt = field_dtype(opts)
+    ws = workspace if workspace is not None else make_workspace(shape, opts)
+    if eps0 is not None:
+        _check_field(eps0, shape, dt, "eps0")
+    eps = torch.empty((6,) + shape, dtype=dt, device=phase.device) if want_eps else None
+    sig = torch.empty((6,) + shape, dtype=dt, device=phase.device) if want_sig else None
+    pr = _problem(phase, lame_tab, lame0)
+    Ea = (ctypes.c_double * 6)(*[float(x) for x in E])
+    sav = (ctypes.c_double * 6)()
+    st, hist, dec = _new_stats(history_cap)
+    rc = _lib.rpm_fft_solve(ctypes.byref(pr), Ea, ctypes.byref(opts), eps0.data_ptr() if eps0 is not None else None,
+                            eps.data_ptr() if eps is not None else None, sig.data_ptr() if sig is not None else None,
+                            sav, ctypes.byref(st), ws.data_ptr(), ws.numel(), _stream())
+    if rc < 0 and check:
+        raise RpmError(rc, "rpm_fft_solve")
+    out = _stats_dict(st, hist, dec)
+    out.update(status=status_string(rc), code=rc, eps=eps, sig=sig, sig_avg=np.array(sav[:]), workspace=ws)
+    return out
+
+
+def effective_tensor(phase, lame_tab, lame0, opts=None, workspace=None, history_cap=100000):
+    """Effective stiffness (Voigt, engineering shear); 6x6 in 3-D, 3x3 (11, 22, 12) in 2-D."""
+    opts = opts or make_options()
+    shape = tuple(phase.shape)
+    two_d = shape[0] == 1
+    nc = 3 if two_d else 6
+    ws = workspace if workspace is not None else make_workspace(shape, opts)
+    pr = _problem(phase, lame_tab, lame0)
+    C = (ctypes.c_double * (nc * nc))()
+    sts = (RpmStats * nc)()
+    keep = []
+    for i in range(nc):
+        hist = np.zeros(history_cap)
+        dec = np.zeros(4096, dtype=np.int32)
+        sts[i].history = hist.ctypes.data_as(_dp)
+        sts[i].history_cap = history_cap
+        sts[i].decisions = dec.ctypes.data_as(_P(ctypes.c_int32))
+        sts[i].decisions_cap = dec.size
+        keep.append((hist, dec))
+    rc = _lib.rpm_fft_effective_tensor(ctypes.byref(pr), ctypes.byref(opts), C, sts, ws.data_ptr(), ws.numel(),
+                                       _stream())
+    if rc < 0:
+        raise RpmError(rc, "rpm_fft_effective_tensor")
+    stats = [_stats_dict(sts[i], keep[i][0], keep[i][1]) for i in range(nc)]
+    return np.array(C[:]).reshape(nc, nc), stats, status_string(rc)
+
+
+def basis_dim(workspace):
+    p = ctypes.c_int32()
+    rc = _lib.rpm_workspace_basis_dim(workspace.data_ptr(), workspace.numel(), ctypes.byref(p), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_workspace_basis_dim")
+    return p.value

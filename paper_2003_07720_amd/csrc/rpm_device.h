@@ -1,0 +1,206 @@
+// Device building blocks of the gfx950 RPM-FFT path: complex arithmetic,
+// radix-2/3/4/8 butterflies, an LDS-resident Stockham FFT stage shared by all
+// pencil passes, and deterministic workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpm {
+
+constexpr int kThreads = 256;     // every pass kernel runs 4 waves of 64
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxStages = 10;
+constexpr int kMaxP = 64;         // basis cap
+
+template <typename T>
+struct cx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+// multiply by s*i, s = +1 or -1
+template <typename T, int S>
+__device__ __forceinline__ cx<T> cmul_si(cx<T> a) { return S > 0 ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x}; }
+
+// Transform lengths are products of the radices of one plan.
+struct Plan {
+    int n;
+    int nst;
+    int rad[kMaxStages];
+};
+
+// ---------------------------------------------------------------------------
+// In-register DFTs of length R with kernel exp(D * 2 pi i j k / R), D = -1
+// (forward) or +1 (inverse).
+// ---------------------------------------------------------------------------
+template <typename T, int D>
+__device__ __forceinline__ void dft2(cx<T>* v)
+{
+    cx<T> a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void dft3(cx<T>* v)
+{
+    const T half = T(0.5);
+    const T s3 = T(0.86602540378443864676372317075294);  // sin(2 pi / 3)
+    cx<T> t1 = cadd(v[1], v[2]);
+    cx<T> t2 = csub(v[1], v[2]);
+    cx<T> m = {v[0].x - half * t1.x, v[0].y - half * t1.y};
+    // D * i * s3 * t2
+    cx<T> r = cmul_si<T, D>(cscale(t2, s3));
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(m, r);
+    v[2] = csub(m, r);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void dft4(cx<T>* v)
+{
+    cx<T> y0 = cadd(v[0], v[2]);
+    cx<T> y1 = csub(v[0], v[2]);
+    cx<T> y2 = cadd(v[1], v[3]);
+    cx<T> y3 = cmul_si<T, D>(csub(v[1], v[3]));
+    v[0] = cadd(y0, y2);
+    v[2] = csub(y0, y2);
+    v[1] = cadd(y1, y3);
+    v[3] = csub(y1, y3);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void dft8(cx<T>* v)
+{
+    const T r2 = T(0.70710678118654752440084436210485);
+    cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+    cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<T, D>(e);
+    dft4<T, D>(o);
+    // w8^k = exp(D 2 pi i k / 8)
+    cx<T> o1 = {r2 * (o[1].x - D * o[1].y), r2 * (o[1].y + D * o[1].x)};
+    cx<T> o2 = cmul_si<T, D>(o[2]);
+    cx<T> o3 = {r2 * (-o[3].x - D * o[3].y), r2 * (-o[3].y + D * o[3].x)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <typename T, int R, int D>
+__device__ __forceinline__ void dftR(cx<T>* v)
+{
+    if constexpr (R == 2) dft2<T, D>(v);
+    else if constexpr (R == 3) dft3<T, D>(v);
+    else if constexpr (R == 4) dft4<T, D>(v);
+    else dft8<T, D>(v);
+}
+
+// One Stockham stage over nseq sequences of length n held in LDS with row
+// stride ss (complex elements).  Ns = product of the radices already applied.
+// tw[e] = exp(-2 pi i e / n), e in [0, n).
+template <typename T, int R, int D>
+__device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns,
+                                          int nseq, int ss, const cx<T>* __restrict__ tw)
+{
+    const int nb = n / R;
+    const int total = nb * nseq;
+    const int tws = n / (Ns * R);
+    for (int g = threadIdx.x; g < total; g += kThreads) {
+        const int s = g / nb;
+        const int j = g - s * nb;
+        const cx<T>* in = src + s * ss;
+        cx<T>* out = dst + s * ss;
+        cx<T> v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = in[j + q * nb];
+        const int k = j % Ns;
+        if (Ns > 1) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                cx<T> w = tw[q * k * tws];
+                if (D > 0) w.y = -w.y;
+                v[q] = cmul(v[q], w);
+            }
+        }
+        dftR<T, R, D>(v);
+        const int o = (j - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) out[o + q * Ns] = v[q];
+    }
+}
+
+// Full LDS FFT of nseq sequences (data in a; b is the ping-pong buffer).
+// Caller must __syncthreads() after filling a.  Returns the buffer that holds
+// the natural-order result; all threads are synchronised on return.
+template <typename T, int D>
+__device__ cx<T>* lds_fft(cx<T>* a, cx<T>* b, const Plan& pl, int nseq, int ss, const cx<T>* tw)
+{
+    int Ns = 1;
+    cx<T>* src = a;
+    cx<T>* dst = b;
+    for (int st = 0; st < pl.nst; ++st) {
+        const int R = pl.rad[st];
+        if (R == 8) fft_stage<T, 8, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else if (R == 4) fft_stage<T, 4, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else if (R == 2) fft_stage<T, 2, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else fft_stage<T, 3, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        __syncthreads();
+        Ns *= R;
+        cx<T>* t = src;
+        src = dst;
+        dst = t;
+    }
+    return src;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic workgroup reductions (fixed shuffle tree, fixed wave order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sums M per-thread values over the workgroup; thread m < M writes the m-th
+// total to dst[m].  lds needs kWaves * M doubles.
+template <int M>
+__device__ __forceinline__ void wg_sum_store(double (&v)[M], double* __restrict__ dst, double* lds)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double s = wave_sum(v[m]);
+        if (lane == 0) lds[wave * M + m] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < M) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) s += lds[w * M + threadIdx.x];
+        dst[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// Frobenius weight of stored tensor component c (shear components count twice).
+__device__ __forceinline__ double frob_w(int c) { return c < 3 ? 1.0 : 2.0; }
+
+}  // namespace rpm

@@ -1,0 +1,873 @@
+// Pass kernels of the gfx950 RPM-FFT path.
+//
+// One application of the Lippmann-Schwinger map (Algorithm 1 lines 5-9; the
+// operator F of Sec. 3) is five pencil passes over an FFT pipeline whose
+// spectrum is transposed as it goes, so that every pass reads or writes whole
+// contiguous rows and the other side in 128-byte (or longer) segments:
+//
+//   xfwd   strain tile -> eps = xi_prev + Z d (RPM recombination), sigma =
+//          C(x):eps in registers, real-to-complex FFT along x (two components
+//          packed per complex FFT), spectrum written as S1[c][kx][z][y]
+//   yfwd   S1 rows along y -> FFT -> S2[c][ky][kx][z]
+//   gamma  S2 rows along z -> FFT -> per frequency t = Gamma0(k):sigma_hat,
+//          equilibrium-error partial sums, <sigma> -> inverse FFT in place
+//   yinv   S2 -> inverse FFT along y -> S1
+//   xinv   S1 -> complex-to-real inverse FFT along x -> xi = eps - t, and the
+//          projections Z^T xi, Z^T eps (FP64 accumulation)
+//
+// In 2-D (nz == 1) the y passes are skipped and gamma runs along y on S1.
+// The k = 0 term of t is N(<eps> - E), so xi = eps - F^-1[Gamma sigma_hat]
+// + (E - <eps>), which is exactly the paper's update with xi_hat(0) = N E.
+#pragma once
+
+#include "rpm_device.h"
+
+namespace rpm {
+
+struct Geo {
+    int nx, ny, nz, nh;    // nh = nx/2 + 1 (half spectrum along x)
+    long long N;           // voxels
+    long long nspec;       // complex entries per component of the half spectrum
+    int ty;                // y rows per x-pass tile
+    int tz;                // z columns per y-pass tile
+    int np;                // pencils per gamma tile
+    int two_d;
+};
+
+// Device-resident solver state (one per workspace).
+struct DevState {
+    int magic;         // kStateMagic once the workspace has been initialised
+    int cfg[5];        // nx, ny, nz, precision, p_max the basis was built for
+    int done;          // 1 once the iteration stopped (any reason)
+    int status;        // 0 converged, 1 not converged, 2 diverged, 3 singular
+    int iters;         // main-loop F applications so far
+    int p;             // basis dimension
+    int singular;      // LU of I - H hit a tiny pivot
+    int max_iter;
+    int pad0, pad1;
+    double tol;
+    double err0;       // error of the starting iterate
+    double err;        // error of the latest iterate
+    double sig_hat0[6];// sigma_hat(0) of the latest F application
+    double mean_eps[6];
+    double E[6];       // prescribed mean strain of the current solve
+    double Ezero[6];   // zeros (mean strain of Jacobian-vector products)
+    double z[kMaxP], zeta[kMaxP], d[kMaxP];
+    double zeta_ring[4][kMaxP];
+    double H[kMaxP * kMaxP];
+    double LU[kMaxP * kMaxP];
+    int piv[kMaxP];
+};
+
+constexpr int kStateMagic = 0x52504d31;
+
+enum { DC_MEAN = 0, DC_ZERO = 1 };   // t_hat(0) = N(<eps> - E) or 0
+enum { OUT_XI = 0, OUT_T = 1 };      // xinv writes eps - t or t
+
+template <typename T>
+struct MaxV;
+template <>
+struct MaxV<float> { static constexpr int v = 8; };
+template <>
+struct MaxV<double> { static constexpr int v = 4; };
+
+// ---------------------------------------------------------------------------
+// x-forward: recombination + constitutive law + R2C FFT along x.
+// grid: nz * (ny / ty) blocks.  LDS: 2 * ty * (nx+1) + nx complex + reduction.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const T* __restrict__ Z, int p,
+                                                   const double* __restrict__ dco, T* __restrict__ eps_out,
+                                                   const uint8_t* __restrict__ phase, const double* __restrict__ lame,
+                                                   int use_ref, double lam0, double mu0, cx<T>* __restrict__ S1,
+                                                   double* __restrict__ part_mean, Geo g, Plan px,
+                                                   const cx<T>* __restrict__ twx, const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int MV = MaxV<T>::v;
+    const int nx = g.nx, ty = g.ty, ss = nx + 1;
+    cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B = A + ty * ss;
+    cx<T>* tw = B + ty * ss;
+    double* red = reinterpret_cast<double*>(tw + nx);
+
+    const int nyt = g.ny / ty;
+    const int z = blockIdx.x / nyt;
+    const int y0 = (blockIdx.x - z * nyt) * ty;
+    const long long base = ((long long)z * g.ny + y0) * nx;  // tile = contiguous rows
+    const int nvox = ty * nx;
+    const long long N = g.N;
+
+    for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
+
+    T sig[MV][6];
+    double msum[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+        const int v = threadIdx.x + i * kThreads;
+        if (v < nvox) {
+            const long long gi = base + v;
+            T e[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) e[c] = xin[c * N + gi];
+            for (int j = 0; j < p; ++j) {
+                const T dj = (T)dco[j];
+                const T* zj = Z + (long long)j * 6 * N + gi;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) e[c] += dj * zj[c * N];
+            }
+            if (eps_out) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) eps_out[c * N + gi] = e[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) msum[c] += (double)e[c];
+            T lam, mu;
+            if (use_ref) {
+                lam = (T)lam0;
+                mu = (T)mu0;
+            } else {
+                const int ph = phase[gi];
+                lam = (T)lame[2 * ph];
+                mu = (T)lame[2 * ph + 1];
+            }
+            const T ltr = lam * (e[0] + e[1] + e[2]);
+            const T m2 = mu + mu;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sig[i][c] = m2 * e[c] + (c < 3 ? ltr : T(0));
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sig[i][c] = T(0);
+        }
+    }
+    if (part_mean) wg_sum_store<6>(msum, part_mean + (long long)blockIdx.x * 6, red);
+
+    const int nh = g.nh;
+    for (int q = 0; q < 3; ++q) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < MV; ++i) {
+            const int v = threadIdx.x + i * kThreads;
+            if (v < nvox) {
+                const int r = v / nx;
+                const int x = v - r * nx;
+                A[r * ss + x] = cx<T>{sig[i][2 * q], sig[i][2 * q + 1]};
+            }
+        }
+        __syncthreads();
+        const cx<T>* R = lds_fft<T, -1>(A, B, px, ty, ss, tw);
+        // split the packed transform into the two real-input spectra
+        cx<T>* outa = S1 + (long long)(2 * q) * g.nspec;
+        cx<T>* outb = S1 + (long long)(2 * q + 1) * g.nspec;
+        for (int t = threadIdx.x; t < nh * ty; t += kThreads) {
+            const int r = t % ty;
+            const int k = t / ty;
+            const cx<T> X = R[r * ss + k];
+            const cx<T> Yc = cconj(R[r * ss + (k == 0 ? 0 : nx - k)]);
+            const cx<T> s = cadd(X, Yc);
+            const cx<T> d = csub(X, Yc);
+            const long long o = ((long long)k * g.nz + z) * g.ny + y0 + r;
+            outa[o] = cx<T>{T(0.5) * s.x, T(0.5) * s.y};
+            outb[o] = cx<T>{T(0.5) * d.y, T(-0.5) * d.x};
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y-forward (FFT along y): S1[c][kx][z][y] -> S2[c][ky][kx][z].
+// grid: 6 * nh * (nz / tz) blocks.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_yfwd(const cx<T>* __restrict__ S1, cx<T>* __restrict__ S2, Geo g,
+                                                   Plan py, const cx<T>* __restrict__ twy,
+                                                   const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ny = g.ny, tz = g.tz, ss = ny + 1;
+    cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B = A + tz * ss;
+    cx<T>* tw = B + tz * ss;
+    const int nzt = g.nz / tz;
+    int b = blockIdx.x;
+    const int zt = b % nzt;
+    b /= nzt;
+    const int kx = b % g.nh;
+    const int c = b / g.nh;
+    const int z0 = zt * tz;
+    for (int i = threadIdx.x; i < ny; i += kThreads) tw[i] = twy[i];
+    const cx<T>* src = S1 + (long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny;
+    for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
+        const int r = t / ny;
+        const int y = t - r * ny;
+        A[r * ss + y] = src[t];
+    }
+    __syncthreads();
+    const cx<T>* R = lds_fft<T, -1>(A, B, py, tz, ss, tw);
+    cx<T>* dst = S2 + (long long)c * g.nspec;
+    for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
+        const int r = t % tz;
+        const int ky = t / tz;
+        dst[((long long)ky * g.nh + kx) * g.nz + z0 + r] = R[r * ss + ky];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y-inverse: S2[c][ky][kx][z] -> inverse FFT along y -> S1[c][kx][z][y].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_yinv(const cx<T>* __restrict__ S2, cx<T>* __restrict__ S1, Geo g,
+                                                   Plan py, const cx<T>* __restrict__ twy,
+                                                   const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ny = g.ny, tz = g.tz, ss = ny + 1;
+    cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B = A + tz * ss;
+    cx<T>* tw = B + tz * ss;
+    const int nzt = g.nz / tz;
+    int b = blockIdx.x;
+    const int zt = b % nzt;
+    b /= nzt;
+    const int kx = b % g.nh;
+    const int c = b / g.nh;
+    const int z0 = zt * tz;
+    for (int i = threadIdx.x; i < ny; i += kThreads) tw[i] = twy[i];
+    const cx<T>* src = S2 + (long long)c * g.nspec;
+    for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
+        const int r = t % tz;
+        const int ky = t / tz;
+        A[r * ss + ky] = src[((long long)ky * g.nh + kx) * g.nz + z0 + r];
+    }
+    __syncthreads();
+    const cx<T>* R = lds_fft<T, +1>(A, B, py, tz, ss, tw);
+    cx<T>* dst = S1 + (long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny;
+    for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
+        const int r = t / ny;
+        const int y = t - r * ny;
+        dst[t] = R[r * ss + y];
+    }
+}
+
+// Wave vector (radians per voxel) of half-spectrum index (kx, ky, kz): signed
+// index in [-n/2, n/2); a Nyquist component takes -pi times the sign of the
+// first non-Nyquist non-zero component in the order z, y, x (+1 if none), so
+// that k(-m) = -k(m) and the inverse transform of Gamma sigma_hat stays real.
+__device__ __forceinline__ void wave_vector(int kx, int ky, int kz, const Geo& g, double* k)
+{
+    const int m[3] = {kx, ky, kz};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    int sgn = 1;
+    bool ny_[3];
+    int s_[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ny_[a] = ((n[a] & 1) == 0) && (2 * m[a] == n[a]);
+        s_[a] = (2 * m[a] < n[a] + 1) ? m[a] : m[a] - n[a];
+    }
+    if (!ny_[2] && s_[2] != 0) sgn = s_[2] > 0 ? 1 : -1;
+    else if (!ny_[1] && s_[1] != 0) sgn = s_[1] > 0 ? 1 : -1;
+    else if (!ny_[0] && s_[0] != 0) sgn = s_[0] > 0 ? 1 : -1;
+    const double pi = 3.14159265358979323846;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) k[a] = ny_[a] ? -pi * sgn : 2.0 * pi * (double)s_[a] / (double)n[a];
+}
+
+// ---------------------------------------------------------------------------
+// gamma: FFT along the last axis, t_hat = Gamma0(k):sigma_hat per frequency
+// (isotropic reference medium: t = sym(n (x) s)/mu0 - c0 (n.s) n (x) n with
+// s = sigma_hat n, c0 = (lam0 + mu0)/(mu0 (lam0 + 2 mu0))), the equilibrium
+// error sum_m |k . sigma_hat|^2 = |k|^2 |s|^2 (half-spectrum weights), the
+// k = 0 term, and the inverse FFT, in place.
+// 3-D: rows along z of S2 (pencil = ky * nh + kx).  2-D: rows along y of S1
+// (pencil = kx, kz = 0).  grid: ceil(npencils / np).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g, Plan pr,
+                                                    const cx<T>* __restrict__ twr, double lam0, double mu0,
+                                                    int dc_mode, const double* __restrict__ E,
+                                                    const double* __restrict__ part_mean, int n_mean,
+                                                    double* __restrict__ part_err, DevState* __restrict__ st,
+                                                    const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nrow = g.two_d ? g.ny : g.nz;
+    const int npen = g.two_d ? g.nh : g.ny * g.nh;
+    const int ss = nrow + 1;
+    const int p0 = blockIdx.x * g.np;
+    const int npl = min(g.np, npen - p0);
+    const int nseq = 6 * npl;
+    cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B = A + 6 * g.np * ss;
+    cx<T>* tw = B + 6 * g.np * ss;
+    double* red = reinterpret_cast<double*>(tw + nrow);
+
+    for (int i = threadIdx.x; i < nrow; i += kThreads) tw[i] = twr[i];
+    for (int c = 0; c < 6; ++c) {
+        const cx<T>* src = S + (long long)c * g.nspec + (long long)p0 * nrow;
+        for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
+            const int pl = t / nrow;
+            const int i = t - pl * nrow;
+            A[(c * npl + pl) * ss + i] = src[t];
+        }
+    }
+    // block 0 holds the k = 0 frequency: finish <eps> from the xfwd partials
+    __shared__ double dc_mean[6];
+    if (blockIdx.x == 0) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        if (dc_mode == DC_MEAN) {
+            for (int b = threadIdx.x; b < n_mean; b += kThreads) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[c] += part_mean[(long long)b * 6 + c];
+            }
+        }
+        wg_sum_store<6>(acc, dc_mean, red);
+    }
+    __syncthreads();
+    cx<T>* R = lds_fft<T, -1>(A, B, pr, nseq, ss, tw);
+
+    const double c0 = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+    const double imu = 1.0 / mu0;
+    double esum = 0.0;
+    for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
+        const int pl = t / nrow;
+        const int i = t - pl * nrow;
+        const int pen = p0 + pl;
+        int kx, ky, kz;
+        if (g.two_d) {
+            kx = pen;
+            ky = i;
+            kz = 0;
+        } else {
+            ky = pen / g.nh;
+            kx = pen - ky * g.nh;
+            kz = i;
+        }
+        cx<T> s[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] = R[(c * npl + pl) * ss + i];
+        cx<T> o[6];
+        if (kx == 0 && ky == 0 && kz == 0) {
+            const double Nd = (double)g.N;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                st->sig_hat0[c] = (double)s[c].x;
+                st->mean_eps[c] = dc_mean[c] / Nd;
+                const double v = (dc_mode == DC_MEAN) ? (dc_mean[c] - Nd * E[c]) : 0.0;
+                o[c] = cx<T>{(T)v, T(0)};
+            }
+        } else {
+            double k[3];
+            wave_vector(kx, ky, kz, g, k);
+            const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+            const double ik = 1.0 / sqrt(kk);
+            const T n0 = (T)(k[0] * ik), n1 = (T)(k[1] * ik), n2 = (T)(k[2] * ik);
+            // s = sigma_hat n with components xx,yy,zz,yz,xz,xy = 0..5
+            const cx<T> sx = cadd(cadd(cscale(s[0], n0), cscale(s[5], n1)), cscale(s[4], n2));
+            const cx<T> sy = cadd(cadd(cscale(s[5], n0), cscale(s[1], n1)), cscale(s[3], n2));
+            const cx<T> sz = cadd(cadd(cscale(s[4], n0), cscale(s[3], n1)), cscale(s[2], n2));
+            const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+            esum += w * kk *
+                    ((double)sx.x * sx.x + (double)sx.y * sx.y + (double)sy.x * sy.x + (double)sy.y * sy.y +
+                     (double)sz.x * sz.x + (double)sz.y * sz.y);
+            const cx<T> a = cadd(cadd(cscale(sx, n0), cscale(sy, n1)), cscale(sz, n2));
+            const T m1 = (T)imu, cc = (T)c0, hm = T(0.5) * (T)imu;
+            o[0] = csub(cscale(sx, m1 * n0), cscale(a, cc * n0 * n0));
+            o[1] = csub(cscale(sy, m1 * n1), cscale(a, cc * n1 * n1));
+            o[2] = csub(cscale(sz, m1 * n2), cscale(a, cc * n2 * n2));
+            o[3] = csub(cadd(cscale(sz, hm * n1), cscale(sy, hm * n2)), cscale(a, cc * n1 * n2));
+            o[4] = csub(cadd(cscale(sz, hm * n0), cscale(sx, hm * n2)), cscale(a, cc * n0 * n2));
+            o[5] = csub(cadd(cscale(sy, hm * n0), cscale(sx, hm * n1)), cscale(a, cc * n0 * n1));
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) R[(c * npl + pl) * ss + i] = o[c];
+    }
+    __syncthreads();
+    const cx<T>* Q = lds_fft<T, +1>(R, R == A ? B : A, pr, nseq, ss, tw);
+    for (int c = 0; c < 6; ++c) {
+        cx<T>* dst = S + (long long)c * g.nspec + (long long)p0 * nrow;
+        for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
+            const int pl = t / nrow;
+            const int i = t - pl * nrow;
+            dst[t] = Q[(c * npl + pl) * ss + i];
+        }
+    }
+    double ev[1] = {esum};
+    if (part_err) wg_sum_store<1>(ev, part_err + blockIdx.x, red);
+}
+
+// ---------------------------------------------------------------------------
+// x-inverse: complex-to-real FFT along x, out = eps - t (OUT_XI) or t
+// (OUT_T), and the FP64 projections sum_x <Z_j, out> and <Z_j, eps>
+// (Frobenius) per block, in chunks of 8 columns.
+// grid: nz * (ny / ty).  part_dots row stride = 2 * ld: [zeta(ld) | z(ld)].
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
+                                                   T* __restrict__ out, int out_mode, const T* __restrict__ Z,
+                                                   int p, int ld, double* __restrict__ part_dots, Geo g, Plan px,
+                                                   const cx<T>* __restrict__ twx, const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int MV = MaxV<T>::v;
+    const int nx = g.nx, ty = g.ty, ss = nx + 1, nh = g.nh;
+    cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B = A + ty * ss;
+    cx<T>* tw = B + ty * ss;
+    double* red = reinterpret_cast<double*>(tw + nx);
+    const int nyt = g.ny / ty;
+    const int z = blockIdx.x / nyt;
+    const int y0 = (blockIdx.x - z * nyt) * ty;
+    const long long base = ((long long)z * g.ny + y0) * nx;
+    const int nvox = ty * nx;
+    const long long N = g.N;
+    const T invN = T(1.0 / (double)N);
+
+    for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
+    T tv[MV][6];
+    for (int q = 0; q < 3; ++q) {
+        __syncthreads();
+        const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
+        const cx<T>* inb = S1 + (long long)(2 * q + 1) * g.nspec;
+        for (int t = threadIdx.x; t < nh * ty; t += kThreads) {
+            const int r = t % ty;
+            const int k = t / ty;
+            const long long o = ((long long)k * g.nz + z) * g.ny + y0 + r;
+            cx<T> a = ina[o];
+            cx<T> b = inb[o];
+            const bool selfc = (k == 0) || (2 * k == nx);
+            if (selfc) {
+                a.y = T(0);
+                b.y = T(0);
+            }
+            A[r * ss + k] = cx<T>{a.x - b.y, a.y + b.x};
+            if (!selfc) A[r * ss + nx - k] = cx<T>{a.x + b.y, b.x - a.y};
+        }
+        __syncthreads();
+        const cx<T>* R = lds_fft<T, +1>(A, B, px, ty, ss, tw);
+#pragma unroll
+        for (int i = 0; i < MV; ++i) {
+            const int v = threadIdx.x + i * kThreads;
+            if (v < nvox) {
+                const int r = v / nx;
+                const int x = v - r * nx;
+                const cx<T> val = R[r * ss + x];
+                tv[i][2 * q] = val.x * invN;
+                tv[i][2 * q + 1] = val.y * invN;
+            }
+        }
+    }
+    // epilogue
+    T ev[MV][6], ov[MV][6];
+#pragma unroll
+    for (int i = 0; i < MV; ++i) {
+        const int v = threadIdx.x + i * kThreads;
+        if (v < nvox) {
+            const long long gi = base + v;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                ev[i][c] = eps[c * N + gi];
+                ov[i][c] = (out_mode == OUT_XI) ? (ev[i][c] - tv[i][c]) : tv[i][c];
+                out[c * N + gi] = ov[i][c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                ev[i][c] = T(0);
+                ov[i][c] = T(0);
+            }
+        }
+    }
+    if (p == 0 || part_dots == nullptr) return;
+    for (int j0 = 0; j0 < p; j0 += 8) {
+        double acc[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int j = j0 + jj;
+            if (j < p) {
+                const T* zj = Z + (long long)j * 6 * N + base;
+#pragma unroll
+                for (int i = 0; i < MV; ++i) {
+                    const int v = threadIdx.x + i * kThreads;
+                    if (v < nvox) {
+#pragma unroll
+                        for (int c = 0; c < 6; ++c) {
+                            const double zc = (double)zj[c * N + v] * frob_w(c);
+                            acc[jj] += zc * (double)ov[i][c];
+                            acc[8 + jj] += zc * (double)ev[i][c];
+                        }
+                    }
+                }
+            }
+        }
+        double* tot = red + kWaves * 16;
+        wg_sum_store<16>(acc, tot, red);
+        if (threadIdx.x < 16) {
+            const int m = threadIdx.x;
+            const int j = j0 + (m & 7);
+            if (j < p) part_dots[(long long)blockIdx.x * 2 * ld + (m < 8 ? 0 : ld) + j] = tot[m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions of per-block partial sums (fixed order: deterministic).
+// out[0] = sum of part_err; out[1 + o] for o < 2p = column map(o) of
+// part_dots (zeta_j at column j, z_j at column ld + j).  grid: 1 + 2p.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_reduce_main(const double* __restrict__ part_err, int G_err,
+                                                          const double* __restrict__ part_dots, int G_dots, int ld,
+                                                          int p, double* __restrict__ out,
+                                                          const int* __restrict__ done)
+{
+    if (done && *done) return;
+    __shared__ double red[kWaves];
+    __shared__ double tot[1];
+    const int o = blockIdx.x;
+    double acc = 0.0;
+    if (o == 0) {
+        if (part_err)
+            for (int b = threadIdx.x; b < G_err; b += kThreads) acc += part_err[b];
+    } else {
+        const int q = o - 1;
+        const int col = q < p ? q : ld + (q - p);
+        for (int b = threadIdx.x; b < G_dots; b += kThreads) acc += part_dots[(long long)b * 2 * ld + col];
+    }
+    double v[1] = {acc};
+    wg_sum_store<1>(v, tot, red);
+    if (threadIdx.x == 0) out[o] = tot[0];
+}
+
+// out[j] = sum_b part[b * ld + j], j < m.  grid: m.
+__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restrict__ part, int G, int ld,
+                                                          double* __restrict__ out)
+{
+    __shared__ double red[kWaves];
+    __shared__ double tot[1];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G; b += kThreads) acc += part[(long long)b * ld + j];
+    double v[1] = {acc};
+    wg_sum_store<1>(v, tot, red);
+    if (threadIdx.x == 0) out[j] = tot[0];
+}
+
+// Solve (I - H) y = r with the stored LU factors (row pivots), single thread.
+__device__ void lu_solve(const DevState* st, int p, const double* r, double* y)
+{
+    double b[kMaxP];
+    for (int i = 0; i < p; ++i) b[i] = r[i];
+    for (int i = 0; i < p; ++i) {  // apply the recorded row swaps
+        const int q = st->piv[i];
+        const double t = b[i];
+        b[i] = b[q];
+        b[q] = t;
+    }
+    for (int i = 0; i < p; ++i) {
+        double s = b[i];
+        for (int j = 0; j < i; ++j) s -= st->LU[i * kMaxP + j] * b[j];
+        b[i] = s;
+    }
+    for (int i = p - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int j = i + 1; j < p; ++j) s -= st->LU[i * kMaxP + j] * y[j];
+        y[i] = s / st->LU[i * kMaxP + i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// finalize (one block): equilibrium error of the iterate that went through F,
+// convergence / divergence / budget tests, and the Newton step on the
+// unstable subspace z' = z + (I - H)^{-1}(zeta - z), giving the recombination
+// coefficients d = z' - zeta for the next xfwd (eps_next = xi + Z d).
+// newton_only: skip the error bookkeeping (used after basis growth).
+// ---------------------------------------------------------------------------
+__global__ void k_finalize(DevState* __restrict__ st, const double* __restrict__ sums, int p, int slot,
+                           int two_d, int newton_only, double* __restrict__ hist, int hist_cap)
+{
+    if (st->done) return;
+    if (threadIdx.x != 0) return;
+    if (!newton_only) {
+        const double* s = st->sig_hat0;
+        const double den = two_d ? (s[0] * s[0] + s[1] * s[1] + 2.0 * s[5] * s[5])
+                                 : (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
+                                    2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+        const double num = sums[0] > 0.0 ? sums[0] : 0.0;
+        const double err = sqrt(num) / sqrt(den);
+        const int it = ++st->iters;
+        if (hist && it - 1 < hist_cap) hist[it - 1] = err;
+        if (it == 1) st->err0 = err;
+        st->err = err;
+        if (!(err == err) || isinf(err) || err > 1e6 * st->err0) {
+            st->status = 2;
+            st->done = 1;
+        } else if (err <= st->tol) {
+            st->status = 0;
+            st->done = 1;
+        } else if (it >= st->max_iter) {
+            st->status = 1;
+            st->done = 1;
+        }
+    }
+    for (int j = 0; j < p; ++j) {
+        st->zeta[j] = sums[1 + j];
+        st->z[j] = sums[1 + p + j];
+        st->zeta_ring[slot][j] = sums[1 + j];
+    }
+    if (st->done) return;
+    if (st->singular) {
+        st->status = 3;
+        st->done = 1;
+        return;
+    }
+    double r[kMaxP], y[kMaxP];
+    for (int j = 0; j < p; ++j) r[j] = st->zeta[j] - st->z[j];
+    if (p > 0) lu_solve(st, p, r, y);
+    for (int j = 0; j < p; ++j) st->d[j] = y[j] - r[j];  // z' - zeta = (z + y) - zeta
+}
+
+// H gains row and column p: H[i][p] = col[i] (i <= p), H[p][j] = row[j] (j < p).
+__global__ void k_border(DevState* __restrict__ st, const double* __restrict__ col, const double* __restrict__ row,
+                         int p)
+{
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i <= p; ++i) st->H[i * kMaxP + p] = col[i];
+    for (int j = 0; j < p; ++j) st->H[p * kMaxP + j] = row[j];
+}
+
+// LU factorisation with partial pivoting of I - H (one thread).
+__global__ void k_factor(DevState* __restrict__ st, int p)
+{
+    if (threadIdx.x != 0) return;
+    double amax = 0.0;
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) {
+            const double a = (i == j ? 1.0 : 0.0) - st->H[i * kMaxP + j];
+            st->LU[i * kMaxP + j] = a;
+            amax = fmax(amax, fabs(a));
+        }
+    int sing = 0;
+    for (int c = 0; c < p; ++c) {
+        int q = c;
+        for (int r = c + 1; r < p; ++r)
+            if (fabs(st->LU[r * kMaxP + c]) > fabs(st->LU[q * kMaxP + c])) q = r;
+        st->piv[c] = q;
+        if (!(fabs(st->LU[q * kMaxP + c]) > 1e-14 * amax)) {
+            sing = 1;
+            break;
+        }
+        if (q != c)
+            for (int j = 0; j < p; ++j) {
+                const double t = st->LU[c * kMaxP + j];
+                st->LU[c * kMaxP + j] = st->LU[q * kMaxP + j];
+                st->LU[q * kMaxP + j] = t;
+            }
+        for (int r = c + 1; r < p; ++r) {
+            const double f = st->LU[r * kMaxP + c] / st->LU[c * kMaxP + c];
+            st->LU[r * kMaxP + c] = f;
+            for (int j = c + 1; j < p; ++j) st->LU[r * kMaxP + j] -= f * st->LU[c * kMaxP + j];
+        }
+    }
+    st->singular = sing;
+    st->p = p;
+}
+
+// ---------------------------------------------------------------------------
+// Voxel-parallel tall-skinny kernels (basis growth, re-projection).
+// Each block covers kChunk voxels; partial sums are per block.
+// ---------------------------------------------------------------------------
+constexpr int kChunk = kThreads * 8;
+
+// D1 = (xa - xb) - Z (za - zb);  D0 = (xb - xc) - Z (zb - zc) when xc != 0.
+// part[b][0..2] = D1.D1, D1.D0, D0.D0 (Frobenius).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ xa, const T* __restrict__ xb,
+                                                          const T* __restrict__ xc, const T* __restrict__ Z, int p,
+                                                          const double* __restrict__ za,
+                                                          const double* __restrict__ zb,
+                                                          const double* __restrict__ zc, double* __restrict__ D1,
+                                                          double* __restrict__ D0, long long N,
+                                                          double* __restrict__ part)
+{
+    __shared__ double red[kWaves * 3 + 3];
+    __shared__ double c1[kMaxP], c0[kMaxP];
+    for (int j = threadIdx.x; j < p; j += kThreads) {
+        c1[j] = za[j] - zb[j];
+        c0[j] = xc ? (zb[j] - zc[j]) : 0.0;
+    }
+    __syncthreads();
+    double acc[3] = {0.0, 0.0, 0.0};
+    const long long b0 = (long long)blockIdx.x * kChunk;
+    for (int i = 0; i < kChunk / kThreads; ++i) {
+        const long long v = b0 + threadIdx.x + i * kThreads;
+        if (v >= N) break;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const long long o = c * N + v;
+            double d1 = (double)xa[o] - (double)xb[o];
+            double d0 = xc ? ((double)xb[o] - (double)xc[o]) : 0.0;
+            for (int j = 0; j < p; ++j) {
+                const double zz = (double)Z[(long long)j * 6 * N + o];
+                d1 -= c1[j] * zz;
+                d0 -= c0[j] * zz;
+            }
+            D1[o] = d1;
+            if (xc) D0[o] = d0;
+            const double w = frob_w(c);
+            acc[0] += w * d1 * d1;
+            acc[1] += w * d1 * d0;
+            acc[2] += w * d0 * d0;
+        }
+    }
+    wg_sum_store<3>(acc, part + (long long)blockIdx.x * 3, red);
+}
+
+// y -= a x ; part[b] = y.y (Frobenius).
+__global__ __launch_bounds__(kThreads) void k_axpy_norm(double* __restrict__ y, const double* __restrict__ x,
+                                                        double a, long long N, double* __restrict__ part)
+{
+    __shared__ double red[kWaves + 1];
+    double acc[1] = {0.0};
+    const long long b0 = (long long)blockIdx.x * kChunk;
+    for (int i = 0; i < kChunk / kThreads; ++i) {
+        const long long v = b0 + threadIdx.x + i * kThreads;
+        if (v >= N) break;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const long long o = c * N + v;
+            const double t = y[o] - a * x[o];
+            y[o] = t;
+            acc[0] += frob_w(c) * t * t;
+        }
+    }
+    wg_sum_store<1>(acc, part + blockIdx.x, red);
+}
+
+// Optionally v -= Z coef (coef device, p values, null = no update), then
+// part[b][j] = <Z_j, v> for j < p and part[b][p] = <v, v>.  ld = p + 1.
+template <typename TV, typename TZ>
+__global__ __launch_bounds__(kThreads) void k_dots(TV* __restrict__ v, const TZ* __restrict__ Z, int p,
+                                                   const double* __restrict__ coef, long long N,
+                                                   double* __restrict__ part)
+{
+    __shared__ double red[kWaves * 9 + 9];
+    __shared__ double cf[kMaxP];
+    if (coef)
+        for (int j = threadIdx.x; j < p; j += kThreads) cf[j] = coef[j];
+    __syncthreads();
+    const long long b0 = (long long)blockIdx.x * kChunk;
+    const int ld = p + 1;
+    if (coef) {
+        for (int i = 0; i < kChunk / kThreads; ++i) {
+            const long long x = b0 + threadIdx.x + i * kThreads;
+            if (x >= N) break;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const long long o = c * N + x;
+                double t = (double)v[o];
+                for (int j = 0; j < p; ++j) t -= cf[j] * (double)Z[(long long)j * 6 * N + o];
+                v[o] = (TV)t;
+            }
+        }
+    }
+    for (int j0 = 0; j0 <= p; j0 += 8) {
+        double acc[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc[m] = 0.0;
+        for (int i = 0; i < kChunk / kThreads; ++i) {
+            const long long x = b0 + threadIdx.x + i * kThreads;
+            if (x >= N) break;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const long long o = c * N + x;
+                const double vv = (double)v[o] * frob_w(c);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int j = j0 + m;
+                    if (j < p) acc[m] += vv * (double)Z[(long long)j * 6 * N + o];
+                    else if (j == p) acc[m] += vv * (double)v[o];
+                }
+            }
+        }
+        double* tot = red + kWaves * 8;
+        wg_sum_store<8>(acc, tot, red);
+        if (threadIdx.x < 8 && j0 + (int)threadIdx.x <= p)
+            part[(long long)blockIdx.x * ld + j0 + threadIdx.x] = tot[threadIdx.x];
+    }
+}
+
+// part[b][j] = <Z_j, a>, part[b][ld + j] = <Z_j, b> (same layout as xinv).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dots2(const T* __restrict__ a, const T* __restrict__ bvec,
+                                                    const T* __restrict__ Z, int p, int ld, long long N,
+                                                    double* __restrict__ part)
+{
+    __shared__ double red[kWaves * 16 + 16];
+    const long long b0 = (long long)blockIdx.x * kChunk;
+    for (int j0 = 0; j0 < p; j0 += 8) {
+        double acc[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) acc[m] = 0.0;
+        for (int i = 0; i < kChunk / kThreads; ++i) {
+            const long long x = b0 + threadIdx.x + i * kThreads;
+            if (x >= N) break;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const long long o = c * N + x;
+                const double av = (double)a[o] * frob_w(c), bv = (double)bvec[o] * frob_w(c);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int j = j0 + m;
+                    if (j < p) {
+                        const double zz = (double)Z[(long long)j * 6 * N + o];
+                        acc[m] += av * zz;
+                        acc[8 + m] += bv * zz;
+                    }
+                }
+            }
+        }
+        double* tot = red + kWaves * 16;
+        wg_sum_store<16>(acc, tot, red);
+        if (threadIdx.x < 16) {
+            const int m = threadIdx.x;
+            const int j = j0 + (m & 7);
+            if (j < p) part[(long long)blockIdx.x * 2 * ld + (m < 8 ? 0 : ld) + j] = tot[m];
+        }
+    }
+}
+
+template <typename TI, typename TO>
+__global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, double scale, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (TO)((double)in[i] * scale);
+}
+
+template <typename T>
+__global__ void k_fill_uniform(T* __restrict__ f, const double* __restrict__ E, long long N)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * N) f[i] = (T)E[i / N];
+}
+
+// sigma = C(x):eps voxel by voxel.
+template <typename T>
+__global__ void k_stress(const T* __restrict__ eps, const uint8_t* __restrict__ phase,
+                         const double* __restrict__ lame, T* __restrict__ sig, long long N)
+{
+    const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= N) return;
+    const int ph = phase[x];
+    const T lam = (T)lame[2 * ph], mu = (T)lame[2 * ph + 1];
+    const T tr = eps[x] + eps[N + x] + eps[2 * N + x];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sig[c * N + x] = (mu + mu) * eps[c * N + x] + (c < 3 ? lam * tr : T(0));
+}
+
+}  // namespace rpm

@@ -1,0 +1,839 @@
+// Host orchestration and C ABI of the gfx950 RPM-FFT solver.
+//
+// The hot loop follows Algorithm 2 of the paper (Algorithm 1 when no basis is
+// kept): every iteration is one application of F (five pencil passes, see
+// rpm_kernels.h) plus one deterministic reduction and one single-workgroup
+// finalize that evaluates the equilibrium error, tests convergence and takes
+// the Newton step on the unstable subspace.  Everything stays on the device;
+// the host reads a 'done' flag every check_every iterations and at the basis
+// growth points (every n_max + 1 iterations), where it needs the QR decision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "rpm_kernels.h"
+#include "rpmfft.h"
+
+using namespace rpm;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kLdsCap = 60 * 1024;  // leaves room for static shared arrays
+constexpr int kMaxN = 512;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool smooth23(int n)
+{
+    if (n < 1) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+Plan make_plan(int n)
+{
+    Plan p{};
+    p.n = n;
+    p.nst = 0;
+    int m = n, twos = 0, threes = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++twos;
+    }
+    while (m % 3 == 0) {
+        m /= 3;
+        ++threes;
+    }
+    while (twos >= 3) {
+        p.rad[p.nst++] = 8;
+        twos -= 3;
+    }
+    if (twos == 2) p.rad[p.nst++] = 4;
+    if (twos == 1) p.rad[p.nst++] = 2;
+    for (int i = 0; i < threes; ++i) p.rad[p.nst++] = 3;
+    return p;
+}
+
+int largest_divisor_leq(int n, int cap)
+{
+    for (int d = std::min(n, std::max(cap, 1)); d >= 1; --d)
+        if (n % d == 0) return d;
+    return 1;
+}
+
+// Tile shapes and LDS bytes of each pass for element type T.
+template <typename T>
+struct Shapes {
+    Geo g;
+    Plan px, py, pr;
+    size_t lds_x, lds_y, lds_g;
+    int G1, Gy, G3, Gg;
+    bool ok;
+};
+
+template <typename T>
+Shapes<T> make_shapes(const int32_t n[3])
+{
+    Shapes<T> s{};
+    const int wsz = (int)sizeof(cx<T>);
+    const int MV = MaxV<T>::v;
+    Geo& g = s.g;
+    g.nx = n[0];
+    g.ny = n[1];
+    g.nz = n[2];
+    g.nh = g.nx / 2 + 1;
+    g.N = (long long)g.nx * g.ny * g.nz;
+    g.nspec = (long long)g.nh * g.ny * g.nz;
+    g.two_d = g.nz == 1 ? 1 : 0;
+    s.ok = true;
+    // x passes: ty rows of nx, at most MV voxels per thread, 128-byte segments
+    int tycap = std::min(128 / wsz, MV * kThreads / g.nx);
+    if (tycap < 1) s.ok = false;
+    g.ty = largest_divisor_leq(g.ny, std::max(tycap, 1));
+    while (g.ty > 1 && (size_t)(2 * g.ty * (g.nx + 1) + g.nx) * wsz + 80 * 8 > (size_t)kLdsCap)
+        g.ty = largest_divisor_leq(g.ny, g.ty - 1);
+    s.lds_x = (size_t)(2 * g.ty * (g.nx + 1) + g.nx) * wsz + 80 * 8;
+    // y passes: tz columns of ny
+    g.tz = largest_divisor_leq(g.nz, 128 / wsz);
+    while (g.tz > 1 && (size_t)(2 * g.tz * (g.ny + 1) + g.ny) * wsz > (size_t)kLdsCap)
+        g.tz = largest_divisor_leq(g.nz, g.tz - 1);
+    s.lds_y = (size_t)(2 * g.tz * (g.ny + 1) + g.ny) * wsz;
+    // gamma pass: np pencils x 6 components along the last axis
+    const int nrow = g.two_d ? g.ny : g.nz;
+    const int npen = g.two_d ? g.nh : g.ny * g.nh;
+    int np = 16;
+    while (np > 1 && (size_t)(12 * np * (nrow + 1) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
+    g.np = np;
+    s.lds_g = (size_t)(12 * np * (nrow + 1) + nrow) * wsz + 80 * 8;
+    if (s.lds_x > (size_t)kLdsCap || s.lds_y > (size_t)kLdsCap || s.lds_g > (size_t)kLdsCap) s.ok = false;
+    if (g.ty * g.nx > MV * kThreads) s.ok = false;
+    s.px = make_plan(g.nx);
+    s.py = make_plan(g.ny);
+    s.pr = make_plan(nrow);
+    s.G1 = g.nz * (g.ny / g.ty);
+    s.Gy = 6 * g.nh * (g.nz / g.tz);
+    s.G3 = (npen + g.np - 1) / g.np;
+    s.Gg = (int)((g.N + kChunk - 1) / kChunk);
+    return s;
+}
+
+struct Layout {
+    size_t st, twx, twy, twr, lame, hist, pmean, perr, pdots, pg, sums, gsum, ring[4], eps, tmp, tmp2, S1, S2, Z,
+        W, D1, D0, total;
+    int ld;
+    long long hist_cap;
+};
+
+template <typename T>
+Layout make_layout(const Shapes<T>& s, const rpm_options* o)
+{
+    Layout L{};
+    const Geo& g = s.g;
+    const size_t fT = (size_t)6 * g.N * sizeof(T);
+    const size_t fD = (size_t)6 * g.N * sizeof(double);
+    const size_t spec = (size_t)6 * g.nspec * sizeof(cx<T>);
+    const int pmax = o->scheme == RPM_SCHEME_RPM ? o->p_max : 0;
+    L.ld = kMaxP;
+    L.hist_cap = (long long)o->max_iter + 1;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.st = take(sizeof(DevState));
+    L.twx = take(sizeof(cx<T>) * kMaxN);
+    L.twy = take(sizeof(cx<T>) * kMaxN);
+    L.twr = take(sizeof(cx<T>) * kMaxN);
+    L.lame = take(sizeof(double) * 512);
+    L.hist = take(sizeof(double) * L.hist_cap);
+    L.pmean = take(sizeof(double) * 6 * s.G1);
+    L.perr = take(sizeof(double) * s.G3);
+    L.pdots = take(sizeof(double) * 2 * L.ld * std::max(s.G1, s.Gg));
+    L.pg = take(sizeof(double) * (kMaxP + 4) * s.Gg);
+    L.sums = take(sizeof(double) * (2 * kMaxP + 8));
+    L.gsum = take(sizeof(double) * (kMaxP + 8));
+    for (int i = 0; i < 4; ++i) L.ring[i] = take(fT);
+    L.eps = take(fT);
+    L.tmp = take(pmax > 0 ? fT : 0);
+    L.tmp2 = take(pmax > 0 ? fT : 0);
+    L.S1 = take(spec);
+    L.S2 = take(g.two_d ? 0 : spec);
+    L.Z = take(fT * pmax);
+    L.W = take(fT * pmax);
+    L.D1 = take(pmax > 0 ? fD : 0);
+    L.D0 = take(pmax > 0 ? fD : 0);
+    L.total = off;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
+// per-call context
+// ---------------------------------------------------------------------------
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Rec {
+        hipEvent_t a, b;
+        int k;
+    };
+    std::vector<Rec> recs;
+    double ms[RPM_NKERNEL] = {0};
+    int n[RPM_NKERNEL] = {0};
+    hipEvent_t get()
+    {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    void harvest()
+    {
+        for (auto& r : recs) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms[r.k] += t;
+                n[r.k] += 1;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    void reset()
+    {
+        harvest();
+        for (int k = 0; k < RPM_NKERNEL; ++k) {
+            ms[k] = 0.0;
+            n[k] = 0;
+        }
+    }
+    ~Prof()
+    {
+        for (auto& r : recs) {
+            hipEventDestroy(r.a);
+            hipEventDestroy(r.b);
+        }
+        for (auto e : pool) hipEventDestroy(e);
+    }
+};
+
+template <typename T>
+struct Ctx {
+    Shapes<T> sh;
+    Layout L;
+    hipStream_t s;
+    char* ws;
+    DevState* st;
+    const uint8_t* phase;
+    double lam0, mu0;
+    int pmax;
+    Prof prof;
+    bool hip_error = false;
+
+    template <typename P>
+    P* at(size_t off) { return reinterpret_cast<P*>(ws + off); }
+    cx<T>* twx() { return at<cx<T>>(L.twx); }
+    cx<T>* twy() { return at<cx<T>>(L.twy); }
+    cx<T>* twr() { return at<cx<T>>(L.twr); }
+    double* lame() { return at<double>(L.lame); }
+    T* ring(int i) { return at<T>(L.ring[i & 3]); }
+    T* eps() { return at<T>(L.eps); }
+    T* Zc(int j) { return at<T>(L.Z) + (size_t)j * 6 * sh.g.N; }
+    T* Wc(int j) { return at<T>(L.W) + (size_t)j * 6 * sh.g.N; }
+    double* sums() { return at<double>(L.sums); }
+    double* gsum() { return at<double>(L.gsum); }
+    double* pdots() { return at<double>(L.pdots); }
+    double* pg() { return at<double>(L.pg); }
+
+    void mark_begin(int k, hipEvent_t& a)
+    {
+        a = nullptr;
+        if (!prof.on) return;
+        a = prof.get();
+        if (a) hipEventRecord(a, s);
+    }
+    void mark_end(int k, hipEvent_t a)
+    {
+        if (!prof.on || !a) return;
+        hipEvent_t b = prof.get();
+        if (!b) return;
+        hipEventRecord(b, s);
+        prof.recs.push_back({a, b, k});
+    }
+    void check_launch()
+    {
+        if (hipGetLastError() != hipSuccess) hip_error = true;
+    }
+};
+
+// One application of the fixed-point map on field xin (optionally corrected
+// by Z d), leaving partial sums for the error and the projections.
+template <typename T>
+void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_inv, T* out, int out_mode,
+           int use_ref, int dc_mode, const double* Edev, int p_dots, const int* done)
+{
+    const Shapes<T>& sh = c.sh;
+    const Geo& g = sh.g;
+    cx<T>* S1 = c.template at<cx<T>>(c.L.S1);
+    cx<T>* S2 = c.template at<cx<T>>(c.L.S2);
+    double* pmean = c.template at<double>(c.L.pmean);
+    double* perr = c.template at<double>(c.L.perr);
+    hipEvent_t ev;
+    c.mark_begin(RPM_K_XFWD, ev);
+    k_xfwd<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d, eps_store,
+                                                  c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, g, sh.px,
+                                                  c.twx(), done);
+    c.mark_end(RPM_K_XFWD, ev);
+    if (!g.two_d) {
+        c.mark_begin(RPM_K_YFWD, ev);
+        k_yfwd<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
+        c.mark_end(RPM_K_YFWD, ev);
+    }
+    c.mark_begin(RPM_K_GAMMA, ev);
+    k_gamma<T><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0, dc_mode,
+                                                   Edev, pmean, sh.G1, perr, c.st, done);
+    c.mark_end(RPM_K_GAMMA, ev);
+    if (!g.two_d) {
+        c.mark_begin(RPM_K_YINV, ev);
+        k_yinv<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py, c.twy(), done);
+        c.mark_end(RPM_K_YINV, ev);
+    }
+    c.mark_begin(RPM_K_XINV, ev);
+    k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, p_dots ? c.Zc(0) : nullptr,
+                                                  p_dots, c.L.ld, p_dots ? c.pdots() : nullptr, g, sh.px, c.twx(),
+                                                  done);
+    c.mark_end(RPM_K_XINV, ev);
+    c.check_launch();
+}
+
+template <typename T>
+void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, int G_dots, const int* done)
+{
+    hipEvent_t ev;
+    c.mark_begin(RPM_K_REDUCE, ev);
+    k_reduce_main<<<1 + 2 * p, kThreads, 0, c.s>>>(newton_only ? nullptr : c.template at<double>(c.L.perr),
+                                                   c.sh.G3, c.pdots(), G_dots, c.L.ld, p, c.sums(), done);
+    c.mark_end(RPM_K_REDUCE, ev);
+    c.mark_begin(RPM_K_FINAL, ev);
+    k_finalize<<<1, 1, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only,
+                                 c.template at<double>(c.L.hist), (int)c.L.hist_cap);
+    c.mark_end(RPM_K_FINAL, ev);
+    c.check_launch();
+}
+
+template <typename T>
+bool sync_read(Ctx<T>& c, void* host, const void* dev, size_t bytes)
+{
+    if (hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c.s) != hipSuccess) return false;
+    if (hipStreamSynchronize(c.s) != hipSuccess) return false;
+    if (c.prof.on) c.prof.harvest();
+    return !c.hip_error;
+}
+
+template <typename T>
+void reduce_cols(Ctx<T>& c, const double* part, int G, int ld, int m, double* out)
+{
+    k_reduce_cols<<<m, kThreads, 0, c.s>>>(part, G, ld, out);
+}
+
+// Initialise or re-validate the workspace header; uploads the tables.
+template <typename T>
+rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool want_reuse, int* p_io)
+{
+    const Geo& g = c.sh.g;
+    DevState hs;
+    if (hipMemcpyAsync(&hs, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.s) != hipSuccess) return RPM_E_HIP;
+    if (hipStreamSynchronize(c.s) != hipSuccess) return RPM_E_HIP;
+    const int cfg[5] = {g.nx, g.ny, g.nz, o->precision, c.pmax};
+    bool same = hs.magic == kStateMagic && std::memcmp(hs.cfg, cfg, sizeof(cfg)) == 0;
+    if (!(same && want_reuse)) {
+        std::memset(&hs, 0, sizeof(hs));
+        hs.magic = kStateMagic;
+        std::memcpy(hs.cfg, cfg, sizeof(cfg));
+        hs.p = 0;
+    }
+    hs.done = 0;
+    hs.status = 1;
+    hs.iters = 0;
+    hs.max_iter = o->max_iter;
+    hs.tol = o->tol;
+    hs.err0 = 0.0;
+    hs.err = 0.0;
+    for (int i = 0; i < 6; ++i) hs.Ezero[i] = 0.0;
+    *p_io = hs.p;
+    // twiddles exp(-2 pi i e / n) computed in long double on the host; the
+    // host buffers stay alive until the stream synchronisation below
+    std::vector<cx<T>> tabs[3];
+    auto tw = [&](int slot, int n, size_t off) -> bool {
+        std::vector<cx<T>>& t = tabs[slot];
+        t.resize(n);
+        for (int e = 0; e < n; ++e) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)e / (long double)n;
+            t[e] = cx<T>{(T)std::cos(ang), (T)std::sin(ang)};
+        }
+        return hipMemcpyAsync(c.ws + off, t.data(), sizeof(cx<T>) * n, hipMemcpyHostToDevice, c.s) == hipSuccess;
+    };
+    if (!tw(0, g.nx, c.L.twx) || !tw(1, g.ny, c.L.twy) || !tw(2, g.two_d ? g.ny : g.nz, c.L.twr)) return RPM_E_HIP;
+    std::vector<double> lt(512, 0.0);
+    for (int i = 0; i < pr->n_phases; ++i) {
+        lt[2 * i] = pr->lame[2 * i];
+        lt[2 * i + 1] = pr->lame[2 * i + 1];
+    }
+    if (hipMemcpyAsync(c.lame(), lt.data(), sizeof(double) * 512, hipMemcpyHostToDevice, c.s) != hipSuccess)
+        return RPM_E_HIP;
+    if (hipMemcpyAsync(c.st, &hs, sizeof(DevState), hipMemcpyHostToDevice, c.s) != hipSuccess) return RPM_E_HIP;
+    if (hipStreamSynchronize(c.s) != hipSuccess) return RPM_E_HIP;
+    return RPM_OK;
+}
+
+template <typename T>
+void set_E(Ctx<T>& c, const double E[6])
+{
+    hipMemcpyAsync(c.st->E, E, sizeof(double) * 6, hipMemcpyHostToDevice, c.s);
+    hipStreamSynchronize(c.s);
+}
+
+// Compatible projection of a T field in place: v <- Gamma0 * (C0 : v), k != 0.
+template <typename T>
+void project_compatible(Ctx<T>& c, T* v, T* out)
+{
+    run_F<T>(c, v, 0, nullptr, v, out, OUT_T, 1, DC_ZERO, c.st->Ezero, 0, nullptr);
+}
+
+// Basis growth In(q, Z) after main-loop F application number it (Sec. 3:
+// QR of the last two differences of q, one or two columns, H bordered by one
+// JVP per column).  Returns the number of columns added, or -1 on HIP error.
+template <typename T>
+int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int growth_index, int* want_out,
+               int* jvps)
+{
+    const long long N = c.sh.g.N;
+    const int Gg = c.sh.Gg;
+    double* D1 = c.template at<double>(c.L.D1);
+    double* D0 = c.template at<double>(c.L.D0);
+    T* tmp = c.template at<T>(c.L.tmp);
+    T* tmp2 = c.template at<T>(c.L.tmp2);
+    const int sa = (it - 1) & 3, sb = (it - 2) & 3, sc = (it - 3) & 3;
+    const bool two = nq >= 3;
+    hipEvent_t ev;
+    c.mark_begin(RPM_K_GROWTH, ev);
+    k_growth_diff<T><<<Gg, kThreads, 0, c.s>>>(c.ring(sa), c.ring(sb), two ? c.ring(sc) : nullptr, c.Zc(0), p,
+                                               c.st->zeta_ring[sa], c.st->zeta_ring[sb], c.st->zeta_ring[sc], D1,
+                                               two ? D0 : nullptr, N, c.pg());
+    reduce_cols(c, c.pg(), Gg, 3, 3, c.gsum());
+    double gram[3];
+    if (!sync_read(c, gram, c.gsum(), sizeof(gram))) return -1;
+    const double T11 = std::sqrt(std::max(gram[0], 0.0));
+    double T22 = 0.0;
+    int want = 0;
+    if (T11 > 0.0) {
+        if (two) {
+            k_axpy_norm<<<Gg, kThreads, 0, c.s>>>(D0, D1, gram[1] / gram[0], N, c.pg());
+            reduce_cols(c, c.pg(), Gg, 1, 1, c.gsum());
+            double n2;
+            if (!sync_read(c, &n2, c.gsum(), sizeof(n2))) return -1;
+            T22 = std::sqrt(std::max(n2, 0.0));
+        }
+        want = (two && T22 > o->kappa * T11) ? 2 : 1;
+    }
+    if (o->replay && growth_index < o->replay_len) want = o->replay[growth_index];
+    *want_out = want;
+    int added = 0;
+    for (int col = 0; col < want && p < c.pmax; ++col) {
+        double* v = col == 0 ? D1 : D0;
+        const double nrm = col == 0 ? T11 : T22;
+        if (!(nrm > 0.0)) continue;
+        if (col == 1 && !two) continue;
+        // normalise, project onto zero-mean compatible fields, back to FP64
+        const long long nel = 6 * N;
+        const int gb = (int)((nel + 255) / 256);
+        k_convert<double, T><<<gb, 256, 0, c.s>>>(v, tmp, 1.0 / nrm, nel);
+        project_compatible<T>(c, tmp, tmp2);
+        k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
+        // two classical Gram-Schmidt passes against Z
+        double* coef = c.gsum();
+        k_dots<double, T><<<Gg, kThreads, 0, c.s>>>(v, c.Zc(0), p, nullptr, N, c.pg());
+        reduce_cols(c, c.pg(), Gg, p + 1, p + 1, coef);
+        k_dots<double, T><<<Gg, kThreads, 0, c.s>>>(v, c.Zc(0), p, coef, N, c.pg());
+        reduce_cols(c, c.pg(), Gg, p + 1, p + 1, c.sums() + kMaxP + 2);
+        k_dots<double, T><<<Gg, kThreads, 0, c.s>>>(v, c.Zc(0), p, c.sums() + kMaxP + 2, N, c.pg());
+        reduce_cols(c, c.pg(), Gg, p + 1, p + 1, coef);
+        double n2;
+        if (!sync_read(c, &n2, coef + p, sizeof(n2))) return -1;
+        const double vn = std::sqrt(std::max(n2, 0.0));
+        if (!(vn > 1e-10)) continue;
+        k_convert<double, T><<<gb, 256, 0, c.s>>>(v, c.Zc(p), 1.0 / vn, nel);
+        // Jacobian-vector product w = F(z_p; E = 0) with the new column of H
+        run_F<T>(c, c.Zc(p), 0, nullptr, c.Zc(p), c.Wc(p), OUT_XI, 0, DC_MEAN, c.st->Ezero, p + 1, nullptr);
+        k_reduce_main<<<1 + 2 * (p + 1), kThreads, 0, c.s>>>(nullptr, 0, c.pdots(), c.sh.G1, c.L.ld, p + 1,
+                                                             c.sums(), nullptr);
+        // new row: <z_p, w_j> for j < p
+        double* row = c.gsum();
+        if (p > 0) {
+            k_dots<T, T><<<Gg, kThreads, 0, c.s>>>(c.Zc(p), c.Wc(0), p, nullptr, N, c.pg());
+            reduce_cols(c, c.pg(), Gg, p + 1, p, row);
+        }
+        k_border<<<1, 1, 0, c.s>>>(c.st, c.sums() + 1, row, p);
+        ++p;
+        ++added;
+        ++*jvps;
+    }
+    if (added > 0) k_factor<<<1, 1, 0, c.s>>>(c.st, p);
+    c.mark_end(RPM_K_GROWTH, ev);
+    c.check_launch();
+    return added;
+}
+
+template <typename T>
+void stats_fill(Ctx<T>& c, rpm_stats* st, const DevState& hs, int jvps, int growth, int p, double secs,
+                const std::vector<int>& decisions)
+{
+    if (!st) return;
+    st->iterations = hs.iters;
+    st->jvps = jvps;
+    st->basis_dim = p;
+    st->growth_events = growth;
+    st->residual = hs.err;
+    st->seconds = secs;
+    if (st->history && st->history_cap > 0) {
+        const int n = std::min(st->history_cap, hs.iters);
+        if (n > 0) {
+            hipMemcpyAsync(st->history, c.template at<double>(c.L.hist), sizeof(double) * n, hipMemcpyDeviceToHost,
+                           c.s);
+            hipStreamSynchronize(c.s);
+        }
+    }
+    if (st->decisions && st->decisions_cap > 0) {
+        for (int i = 0; i < std::min((int)decisions.size(), st->decisions_cap); ++i) st->decisions[i] = decisions[i];
+    }
+    for (int k = 0; k < RPM_NKERNEL; ++k) {
+        st->kernel_ms[k] = c.prof.ms[k];
+        st->kernel_launches[k] = c.prof.n[k];
+    }
+}
+
+// One solve (Algorithm 1 or 2) for the mean strain E.
+template <typename T>
+rpm_status solve_impl(Ctx<T>& c, const rpm_problem* pr, const double E[6], const rpm_options* o, const T* eps0,
+                      T* eps_out, T* sig_out, double* sig_avg, rpm_stats* st, bool reuse)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const Geo& g = c.sh.g;
+    const long long N = g.N;
+    int p = 0;
+    rpm_status rs = prepare(c, pr, o, reuse, &p);
+    if (rs != RPM_OK) return rs;
+    set_E(c, E);
+    const bool rpm = o->scheme == RPM_SCHEME_RPM && c.pmax > 0;
+    const int* done = &c.st->done;
+    int jvps = 0, growth = 0;
+    std::vector<int> decisions;
+
+    // initial iterate eps^0 = E (or the supplied start) and xi^0 = F(eps^0)
+    if (eps0) {
+        hipMemcpyAsync(c.eps(), eps0, sizeof(T) * 6 * N, hipMemcpyDeviceToDevice, c.s);
+    } else {
+        const long long nel = 6 * N;
+        k_fill_uniform<T><<<(int)((nel + 255) / 256), 256, 0, c.s>>>(c.eps(), c.st->E, N);
+    }
+    run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(1), OUT_XI, 0, DC_MEAN, c.st->E, rpm ? p : 0, done);
+    reduce_and_finalize(c, rpm ? p : 0, 1, 0, c.sh.G1, done);
+
+    int it = 1, nu = 0, nq = 0;
+    int hdone = 0;
+    const int check = std::max(1, o->check_every);
+    for (;;) {
+        const bool at_growth = rpm && (nu > o->n_max) && p < c.pmax;
+        if (at_growth || (it % check) == 0 || it >= o->max_iter) {
+            int flags[4];
+            if (!sync_read(c, flags, &c.st->done, sizeof(flags))) return RPM_E_HIP;
+            hdone = flags[0];
+            if (hdone || flags[2] >= o->max_iter) break;
+            if (at_growth) {
+                int want = 0;
+                const int added = grow_basis(c, it, nq, p, o, growth, &want, &jvps);
+                if (added < 0) return RPM_E_HIP;
+                decisions.push_back(want);
+                ++growth;
+                nu = 0;
+                nq = 0;
+                // projections of the current pair (eps, xi) on the grown basis, Newton step
+                k_dots2<T><<<c.sh.Gg, kThreads, 0, c.s>>>(c.ring(it), c.eps(), c.Zc(0), p, c.L.ld, N, c.pdots());
+                reduce_and_finalize(c, p, it, 1, c.sh.Gg, done);
+            }
+        }
+        // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step
+        ++it;
+        const T* xprev = c.ring(it - 1);
+        if (rpm) {
+            run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, p, done);
+        } else {
+            run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, 0, done);
+        }
+        reduce_and_finalize(c, rpm ? p : 0, it, 0, c.sh.G1, done);
+        ++nu;
+        ++nq;
+    }
+    DevState hs;
+    if (!sync_read(c, &hs, c.st, sizeof(hs))) return RPM_E_HIP;
+    // the iterate whose error was evaluated last
+    const int itf = std::max(hs.iters, 1);
+    const T* efin = (itf == 1 || rpm) ? c.eps() : c.ring(itf - 1);
+    if (eps_out) hipMemcpyAsync(eps_out, efin, sizeof(T) * 6 * N, hipMemcpyDeviceToDevice, c.s);
+    if (sig_out) {
+        k_stress<T><<<(int)((N + 255) / 256), 256, 0, c.s>>>(efin, c.phase, c.lame(), sig_out, N);
+    }
+    if (sig_avg)
+        for (int i = 0; i < 6; ++i) sig_avg[i] = hs.sig_hat0[i] / (double)N;
+    if (hipStreamSynchronize(c.s) != hipSuccess || c.hip_error) return RPM_E_HIP;
+    if (c.prof.on) c.prof.harvest();
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats_fill(c, st, hs, jvps, growth, p, secs, decisions);
+    switch (hs.status) {
+        case 0: return RPM_OK;
+        case 2: return RPM_DIVERGED;
+        case 3: return RPM_SINGULAR;
+        default: return RPM_NOT_CONVERGED;
+    }
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+rpm_status validate(const rpm_problem* pr, const rpm_options* o)
+{
+    if (!pr || !o || !pr->lame) return RPM_E_INVALID;
+    if (pr->n_phases < 1 || pr->n_phases > 256) return RPM_E_INVALID;
+    for (int a = 0; a < 3; ++a) {
+        const int n = pr->n[a];
+        if (a == 2 && n == 1) continue;
+        if (n < 2 || n > kMaxN || !smooth23(n)) return RPM_E_UNSUPPORTED_SIZE;
+    }
+    for (int i = 0; i < pr->n_phases; ++i) {
+        const double l = pr->lame[2 * i], m = pr->lame[2 * i + 1];
+        if (!finite(l) || !finite(m) || m < 0.0 || 3.0 * l + 2.0 * m < 0.0) return RPM_E_INVALID;
+    }
+    const double l0 = pr->lame0[0], m0 = pr->lame0[1];
+    if (!finite(l0) || !finite(m0) || !(m0 > 0.0) || !(3.0 * l0 + 2.0 * m0 > 0.0)) return RPM_E_INVALID;
+    if (!finite(o->tol) || !(o->tol > 0.0)) return RPM_E_INVALID;
+    if (o->max_iter < 1 || o->n_max < 1 || o->p_max < 0 || o->p_max > kMaxP) return RPM_E_INVALID;
+    if (!finite(o->kappa) || o->kappa < 0.0 || o->kappa > 1.0) return RPM_E_INVALID;
+    if (o->scheme != RPM_SCHEME_BASIC && o->scheme != RPM_SCHEME_RPM) return RPM_E_INVALID;
+    if (o->precision != RPM_FP64 && o->precision != RPM_FP32) return RPM_E_INVALID;
+    if (o->check_every < 1) return RPM_E_INVALID;
+    if (o->replay_len < 0 || (o->replay_len > 0 && !o->replay)) return RPM_E_INVALID;
+    return RPM_OK;
+}
+
+template <typename T>
+rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void* ws, size_t ws_bytes,
+                    void* stream)
+{
+    c.sh = make_shapes<T>(pr->n);
+    if (!c.sh.ok) return RPM_E_UNSUPPORTED_SIZE;
+    c.L = make_layout<T>(c.sh, o);
+    if (!ws || ws_bytes < c.L.total) return RPM_E_WORKSPACE;
+    if (!pr->phase) return RPM_E_INVALID;
+    c.s = (hipStream_t)stream;
+    c.ws = (char*)ws;
+    c.st = reinterpret_cast<DevState*>(c.ws + c.L.st);
+    c.phase = pr->phase;
+    c.lam0 = pr->lame0[0];
+    c.mu0 = pr->lame0[1];
+    c.pmax = o->scheme == RPM_SCHEME_RPM ? o->p_max : 0;
+    c.prof.on = o->profile != 0;
+    return RPM_OK;
+}
+
+bool finite6(const double* E)
+{
+    for (int i = 0; i < 6; ++i)
+        if (!finite(E[i])) return false;
+    return true;
+}
+
+template <typename T>
+rpm_status solve_typed(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps0,
+                       void* eps_out, void* sig_out, double sig_avg[6], rpm_stats* st, void* ws, size_t ws_bytes,
+                       void* stream)
+{
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    return solve_impl<T>(c, pr, E, o, (const T*)eps0, (T*)eps_out, (T*)sig_out, sig_avg, st, o->reuse_basis != 0);
+}
+
+template <typename T>
+rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps, void* xi,
+                       double* err, double* sig_avg, void* ws, size_t ws_bytes, void* stream)
+{
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    int p = 0;
+    rs = prepare(c, pr, o, false, &p);
+    if (rs != RPM_OK) return rs;
+    set_E(c, E);
+    run_F<T>(c, (const T*)eps, 0, nullptr, (const T*)eps, (T*)xi, OUT_XI, 0, DC_MEAN, c.st->E, 0, nullptr);
+    reduce_and_finalize(c, 0, 1, 0, c.sh.G1, nullptr);
+    DevState hs;
+    if (!sync_read(c, &hs, c.st, sizeof(hs))) return RPM_E_HIP;
+    if (err) *err = hs.err;
+    if (sig_avg)
+        for (int i = 0; i < 6; ++i) sig_avg[i] = hs.sig_hat0[i] / (double)c.sh.g.N;
+    return RPM_OK;
+}
+
+template <typename T>
+rpm_status eff_typed(const rpm_problem* pr, const rpm_options* o, double* C, rpm_stats* st, void* ws,
+                     size_t ws_bytes, void* stream)
+{
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    const bool two_d = pr->n[2] == 1;
+    const int cases3[3] = {0, 1, 5};
+    const int nc = two_d ? 3 : 6;
+    rpm_status worst = RPM_OK;
+    for (int col = 0; col < nc; ++col) {
+        const int j = two_d ? cases3[col] : col;
+        double E[6] = {0, 0, 0, 0, 0, 0};
+        E[j] = j < 3 ? 1.0 : 0.5;
+        double sav[6];
+        const bool reuse = o->reuse_basis != 0;
+        c.prof.reset();
+        rs = solve_impl<T>(c, pr, E, o, nullptr, nullptr, nullptr, sav, st ? st + col : nullptr, reuse);
+        if (rs < 0) return rs;
+        if (rs != RPM_OK && worst == RPM_OK) worst = rs;
+        for (int row = 0; row < nc; ++row) {
+            const int i = two_d ? cases3[row] : row;
+            C[row * nc + col] = sav[i];
+        }
+    }
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rpm_default_options(rpm_options* o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-6;
+    o->max_iter = 10000;
+    o->n_max = 10;
+    o->p_max = 32;
+    o->kappa = 0.1;
+    o->scheme = RPM_SCHEME_RPM;
+    o->precision = RPM_FP64;
+    o->reuse_basis = 0;
+    o->check_every = 16;
+    o->replay = nullptr;
+    o->replay_len = 0;
+    o->profile = 0;
+}
+
+rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
+{
+    if (!lam || !mu || !std::isfinite(E) || !std::isfinite(nu) || nu >= 0.5 || nu <= -1.0) return RPM_E_INVALID;
+    *lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu));
+    *mu = E / (2.0 * (1.0 + nu));
+    return RPM_OK;
+}
+
+rpm_status rpm_workspace_size(const int32_t n[3], const rpm_options* o, size_t* bytes)
+{
+    if (!n || !o || !bytes) return RPM_E_INVALID;
+    for (int a = 0; a < 3; ++a) {
+        if (a == 2 && n[a] == 1) continue;
+        if (n[a] < 2 || n[a] > kMaxN || !smooth23(n[a])) return RPM_E_UNSUPPORTED_SIZE;
+    }
+    if (o->max_iter < 1 || o->p_max < 0 || o->p_max > kMaxP) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64) {
+        Shapes<double> s = make_shapes<double>(n);
+        if (!s.ok) return RPM_E_UNSUPPORTED_SIZE;
+        *bytes = make_layout<double>(s, o).total;
+    } else if (o->precision == RPM_FP32) {
+        Shapes<float> s = make_shapes<float>(n);
+        if (!s.ok) return RPM_E_UNSUPPORTED_SIZE;
+        *bytes = make_layout<float>(s, o).total;
+    } else {
+        return RPM_E_INVALID;
+    }
+    return RPM_OK;
+}
+
+rpm_status rpm_fft_apply(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps, void* xi,
+                         double* err, double sig_avg[6], void* workspace, size_t ws_bytes, void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (!E || !finite6(E) || !eps || !xi || eps == xi) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64)
+        return apply_typed<double>(pr, E, o, eps, xi, err, sig_avg, workspace, ws_bytes, hip_stream);
+    return apply_typed<float>(pr, E, o, eps, xi, err, sig_avg, workspace, ws_bytes, hip_stream);
+}
+
+rpm_status rpm_fft_solve(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps0,
+                         void* eps_out, void* sig_out, double sig_avg[6], rpm_stats* st, void* workspace,
+                         size_t ws_bytes, void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (!E || !finite6(E)) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64)
+        return solve_typed<double>(pr, E, o, eps0, eps_out, sig_out, sig_avg, st, workspace, ws_bytes, hip_stream);
+    return solve_typed<float>(pr, E, o, eps0, eps_out, sig_out, sig_avg, st, workspace, ws_bytes, hip_stream);
+}
+
+rpm_status rpm_fft_effective_tensor(const rpm_problem* pr, const rpm_options* o, double* C_eff, rpm_stats* st,
+                                    void* workspace, size_t ws_bytes, void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (!C_eff) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64) return eff_typed<double>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
+    return eff_typed<float>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
+}
+
+rpm_status rpm_workspace_basis_dim(const void* workspace, size_t ws_bytes, int32_t* p, void* hip_stream)
+{
+    if (!workspace || !p || ws_bytes < sizeof(DevState)) return RPM_E_INVALID;
+    DevState hs;
+    if (hipMemcpyAsync(&hs, workspace, sizeof(DevState), hipMemcpyDeviceToHost, (hipStream_t)hip_stream) !=
+        hipSuccess)
+        return RPM_E_HIP;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return RPM_E_HIP;
+    *p = hs.magic == kStateMagic ? hs.p : 0;
+    return RPM_OK;
+}
+
+const char* rpm_status_string(rpm_status s)
+{
+    switch (s) {
+        case RPM_OK: return "RPM_OK";
+        case RPM_NOT_CONVERGED: return "RPM_NOT_CONVERGED";
+        case RPM_DIVERGED: return "RPM_DIVERGED";
+        case RPM_SINGULAR: return "RPM_SINGULAR";
+        case RPM_E_INVALID: return "RPM_E_INVALID";
+        case RPM_E_UNSUPPORTED_SIZE: return "RPM_E_UNSUPPORTED_SIZE";
+        case RPM_E_WORKSPACE: return "RPM_E_WORKSPACE";
+        case RPM_E_HIP: return "RPM_E_HIP";
+    }
+    return "RPM_UNKNOWN";
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: FP64 fields within 1e-10 relative (the stated target), FP64 map
+applications within 1e-12; FP32 map applications within 2e-5 relative of the
+field scale (FP32 FFT rounding, log2 N growth).  Where RPM trajectories depend
+on discrete growth decisions the oracle runs first and its decisions are
+replayed into the GPU solve; iteration counts, basis size and error histories
+must then agree.
+"""
+import numpy as np
+import pytest
+
+import closed_forms as CF
+import oracle as O
+from paper_2003_07720_amd import microstructure as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_2003_07720_amd import binding
+
+    return binding
+
+
+def dev(a, dtype=None):
+    import torch
+
+    t = torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    return t.to(dtype) if dtype is not None else t
+
+
+def gpu_lame(B, phases):
+    return np.array([B.lame_from_young(*p) for p in phases])
+
+
+PHASES3 = [(1.0, 0.3), (7.0, 0.25), (0.2, 0.4)]
+
+GRIDS = [(1, 32, 32), (1, 6, 8), (1, 48, 12), (4, 6, 8), (2, 4, 6), (8, 8, 8), (12, 16, 6), (9, 3, 6),
+         (3, 9, 27), (16, 16, 16), (6, 96, 4), (32, 12, 48)]
+
+
+@pytest.mark.parametrize("shape", GRIDS, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fmap_parity(B, shape, prec):
+    import torch
+
+    print(f"fmap parity {shape} {prec}", flush=True)
+    ph = M.random_phases(shape, 3, seed=sum(shape))
+    eps = M.random_field(shape, seed=7 + sum(shape), scale=0.01)
+    E = np.array([0.01, -0.003, 0.002, 0.001, -0.002, 0.004])
+    l0 = (2.0, 1.5)
+    ref_xi, ref_err, ref_sav, _ = O.fmap(ph, O.lame_table(PHASES3), l0, E, eps)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    opts = B.make_options(precision=prec, scheme="basic")
+    xi, err, sav = B.fft_apply(dev(ph), gpu_lame(B, PHASES3), l0, E, dev(eps, dt), opts)
+    xi = xi.double().cpu().numpy()
+    scale = np.abs(ref_xi).max()
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    assert np.abs(xi - ref_xi).max() <= tol * scale
+    assert abs(err - ref_err) <= (1e-11 if prec == "fp64" else 2e-4) * ref_err
+    np.testing.assert_allclose(sav, ref_sav, rtol=0, atol=tol * np.abs(ref_sav).max() * 10)
+
+
+def _disk32(B):
+    w = M.workload_disk32()
+    return w, O.lame_table(w["phases"]), O.lame(*w["ref"]), gpu_lame(B, w["phases"]), B.lame_from_young(*w["ref"])
+
+
+def test_basic_disk32_fp64(B):
+    w, lt, l0, glt, gl0 = _disk32(B)
+    ref = O.solve(w["phase"], lt, l0, w["E"], scheme="basic", tol=w["tol"])
+    g = B.fft_solve(dev(w["phase"]), glt, gl0, w["E"], B.make_options(scheme="basic", tol=w["tol"]))
+    assert g["status"] == "RPM_OK" and ref["status"] == "converged"
+    assert g["iterations"] == ref["iterations"]
+    eps = g["eps"].cpu().numpy()
+    assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
+    # the error is normalised by |sigma_hat(0)|; FP64 rounding of the spectrum leaves ~1e-15 absolute
+    np.testing.assert_allclose(g["history"], ref["history"], rtol=1e-9, atol=1e-14)
+    np.testing.assert_allclose(g["sig_avg"], ref["sig_avg"], rtol=0, atol=1e-12 * np.abs(ref["sig_avg"]).max())
+
+
+@pytest.mark.parametrize("n_max", [10, 3])
+def test_rpm_disk32_fp64(B, n_max):
+    w, lt, l0, glt, gl0 = _disk32(B)
+    ref = O.solve(w["phase"], lt, l0, w["E"], scheme="rpm", tol=w["tol"], n_max=n_max, p_max=32)
+    opts = B.make_options(scheme="rpm", tol=w["tol"], n_max=n_max, p_max=32, replay=list(ref["decisions"]))
+    g = B.fft_solve(dev(w["phase"]), glt, gl0, w["E"], opts)
+    assert g["status"] == "RPM_OK" and ref["status"] == "converged"
+    assert g["iterations"] == ref["iterations"]
+    assert g["basis_dim"] == ref["p"] and g["jvps"] == ref["jvps"]
+    eps = g["eps"].cpu().numpy()
+    assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
+    np.testing.assert_allclose(g["history"], ref["history"], rtol=1e-9, atol=1e-14)
+    # without replay the GPU takes the same decisions on this case
+    g2 = B.fft_solve(dev(w["phase"]), glt, gl0, w["E"],
+                     B.make_options(scheme="rpm", tol=w["tol"], n_max=n_max, p_max=32))
+    assert list(g2["decisions"]) == list(ref["decisions"])
+
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 12, 16)], ids=lambda s: "x".join(map(str, s)))
+def test_rpm_random_3d_fp64(B, shape):
+    ph = M.random_phases(shape, 2, seed=101)
+    phases = [(1.0, 0.3), (100.0, 0.3)]
+    E = np.array([0.0, 0.0, 0.01, 0.0, 0.003, 0.0])
+    l0 = O.lame(50.5, 0.3)
+    ref = O.solve(ph, O.lame_table(phases), l0, E, scheme="rpm", tol=1e-9, n_max=6, p_max=16, max_iter=3000)
+    opts = B.make_options(scheme="rpm", tol=1e-9, n_max=6, p_max=16, max_iter=3000, replay=list(ref["decisions"]))
+    g = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(50.5, 0.3), E, opts)
+    assert ref["status"] == "converged" and g["status"] == "RPM_OK"
+    assert g["iterations"] == ref["iterations"] and g["basis_dim"] == ref["p"]
+    eps = g["eps"].cpu().numpy()
+    assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
+
+
+def test_effective_tensor_2d_fp64(B):
+    w, lt, l0, glt, gl0 = _disk32(B)
+    Cref, runs = O.effective_tensor(w["phase"], lt, l0, scheme="rpm", tol=1e-10, max_iter=3000)
+    C, stats, st = B.effective_tensor(dev(w["phase"]), glt, gl0,
+                                      B.make_options(scheme="rpm", tol=1e-10, max_iter=3000, reuse_basis=1))
+    assert st == "RPM_OK"
+    assert np.abs(C - Cref).max() <= 1e-9 * np.abs(Cref).max()
+    assert [s["iterations"] for s in stats] == [r["iterations"] for r in runs]
+
+
+def test_homogeneous_one_iteration(B):
+    shape = (4, 8, 6)
+    ph = np.zeros(shape, np.uint8)
+    E = np.array([0.01, 0.002, -0.003, 0.001, 0.0, 0.002])
+    g = B.fft_solve(dev(ph), [B.lame_from_young(2.0, 0.3)], B.lame_from_young(5.0, 0.2), E,
+                    B.make_options(tol=1e-12))
+    assert g["status"] == "RPM_OK" and g["iterations"] == 1 and g["residual"] < 1e-14
+    np.testing.assert_allclose(g["eps"].cpu().numpy(), np.broadcast_to(E[:, None, None, None], (6,) + shape),
+                               atol=1e-16)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_laminate_exact_gpu(B, prec):
+    shape = (8, 4, 4)
+    ph = M.laminate((4, 4, 8), [0, 1, 1, 0, 2, 0, 0, 1], axis=2)
+    phases = [(1.0, 0.3), (8.0, 0.25), (3.0, 0.35)]
+    lt = np.array([CF.lame(*p) for p in phases])
+    E = np.array([0.01, 0.002, -0.003, 0.004, -0.001, 0.002])
+    ref_eps, ref_sig = CF.laminate_solution(ph, lt, E, axis=2)
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    g = B.fft_solve(dev(ph), lt, CF.lame(5.0, 0.3), E, B.make_options(tol=tol, precision=prec, max_iter=5000))
+    assert g["status"] == "RPM_OK"
+    bar = 1e-12 if prec == "fp64" else 1e-6
+    assert np.abs(g["eps"].double().cpu().numpy() - ref_eps).max() <= bar * np.abs(ref_eps).max() * 10
+    np.testing.assert_allclose(g["sig_avg"], ref_sig, atol=bar * np.abs(ref_sig).max() * 10)
+
+
+def test_status_codes(B):
+    shape = (4, 4, 4)
+    ph = M.random_phases(shape, 2, seed=51)
+    phases = [(1.0, 0.3), (100.0, 0.3)]
+    E = np.array([0.01, 0, 0, 0, 0, 0])
+    g = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(50.5, 0.3), E,
+                    B.make_options(tol=1e-12, max_iter=3, scheme="basic"))
+    assert g["status"] == "RPM_NOT_CONVERGED" and g["iterations"] == 3
+    ref = O.solve(ph, O.lame_table(phases), O.lame(30.0, 0.3), E, scheme="basic", tol=1e-8, max_iter=5000)
+    g = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(30.0, 0.3), E,
+                    B.make_options(tol=1e-8, max_iter=5000, scheme="basic"))
+    assert ref["status"] == "diverged" and g["status"] == "RPM_DIVERGED"
+    assert g["iterations"] == ref["iterations"]
+
+
+def test_deterministic(B):
+    shape = (8, 8, 8)
+    ph = M.random_phases(shape, 2, seed=61)
+    phases = [(1.0, 0.3), (50.0, 0.3)]
+    E = np.array([0.01, 0, 0, 0, 0, 0.002])
+    opts = B.make_options(tol=1e-9, n_max=5)
+    a = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(25.5, 0.3), E, opts)
+    b = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(25.5, 0.3), E, opts)
+    assert a["iterations"] == b["iterations"]
+    assert bool((a["eps"] == b["eps"]).all())
+    assert np.array_equal(a["history"], b["history"])
