@@ -1,0 +1,160 @@
+"""Benchmark: voxel-iterations/s and time to a 1e-6 equilibrium error of RPM-FFT
+on the 128^3 void cell (30 % spherical voids of stiffness 1e-8, matrix E = 1,
+nu = 0.3, mean strain eps_zz = 0.01), FP32 fields and FFTs with FP64 RPM steps,
+basis capped at 32, n_max = 10.
+
+A step is one iteration of the solver: one application of the fixed-point map
+with the RPM recombination, projections, Newton step and (every n_max + 1
+iterations) basis growth.  The timed region is one solve of exactly K steps
+from the uniform start; value = voxels x (steps + JVP map applications) / s.
+
+Prints one JSON line (see the keys below).  --gpus above 1 is refused: this
+build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--seed", type=int, default=3000)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--ttt-iters", type=int, default=4000, help="iteration cap of the time-to-tolerance solve")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle map applications in the CPU sample")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: --gpus {a.gpus} refused: this build runs on a single GPU (one process, one device); "
+              f"run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2003_07720_amd import binding as B
+    from paper_2003_07720_amd import microstructure as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = M.workload_voids128(seed=a.seed, n=a.n)
+    phases = w["phases"]
+    E = w["E"]
+    lt = np.array([B.lame_from_young(*p) for p in phases])
+    E0 = 0.5 * (phases[0][0] + phases[1][0])  # arithmetic mean of the phase moduli
+    l0 = B.lame_from_young(E0, 0.3)
+    phase = torch.from_numpy(w["phase"]).to("cuda")
+    N = phase.numel()
+    common = dict(scheme="rpm", precision=a.precision, n_max=10, p_max=32, kappa=0.1, tol=a.tol, check_every=32)
+    ws = B.make_workspace(tuple(phase.shape), B.make_options(max_iter=max(a.steps, a.ttt_iters, a.warmup) + 1,
+                                                            **common))
+    print(f"bench: workload {a.n}^3 voids vf={w['info']['vf']:.4f} ({w['info']['n_spheres']} spheres), "
+          f"{a.precision}, warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
+
+    # warm-up (untimed)
+    if a.warmup > 0:
+        B.fft_solve(phase, lt, l0, E, B.make_options(max_iter=a.warmup, **common), workspace=ws, want_eps=False)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps, kernel durations from HIP events on the solver's stream
+    opts = B.make_options(max_iter=a.steps, profile=1, **common)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = B.fft_solve(phase, lt, l0, E, opts, workspace=ws, want_eps=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    el = t1 - t0
+    steps = r["iterations"]
+    fcalls = steps + r["jvps"]
+    value = N * fcalls / el
+    print(f"bench: {steps} steps, {r['jvps']} JVPs, p={r['basis_dim']}, residual {r['residual']:.3e}, "
+          f"{el * 1e3:.1f} ms", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel class
+    kms = r["kernel_ms"]
+    dom = max((k for k in kms if r["kernel_bytes"][k] > 0), key=lambda k: kms[k])
+    launches = r["kernel_launches"][dom]
+    avg_ms = kms[dom] / launches
+    bytes_per_launch = r["kernel_bytes"][dom] / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    per_kernel = {k: dict(ms_total=round(kms[k], 4), launches=r["kernel_launches"][k],
+                          avg_us=round(1e3 * kms[k] / max(r["kernel_launches"][k], 1), 3),
+                          gbs=round(r["kernel_bytes"][k] / max(kms[k], 1e-12) / 1e6, 1))
+                  for k in kms if r["kernel_launches"][k] > 0}
+
+    # time to tolerance (plain RPM, uniform start)
+    ttt = None
+    ttt_info = {}
+    if not a.no_ttt:
+        o2 = B.make_options(max_iter=a.ttt_iters, **common)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        r2 = B.fft_solve(phase, lt, l0, E, o2, workspace=ws, want_eps=False, history_cap=a.ttt_iters + 1)
+        torch.cuda.synchronize()
+        s1 = time.perf_counter()
+        ttt_info = dict(status=r2["status"], iterations=r2["iterations"], jvps=r2["jvps"], p=r2["basis_dim"],
+                        residual=r2["residual"], seconds=round(s1 - s0, 4))
+        if r2["status"] == "RPM_OK":
+            ttt = s1 - s0
+        print(f"bench: time-to-tol solve {ttt_info}", file=sys.stderr, flush=True)
+
+    # CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if not a.no_cpu:
+        import oracle as O
+
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        c0 = time.perf_counter()
+        rc = O.solve(w["phase"], O.lame_table(phases), O.lame(E0, 0.3), E, scheme="rpm", tol=a.tol,
+                     max_iter=a.cpu_steps, n_max=10, p_max=32)
+        c1 = time.perf_counter()
+        cpu = dict(value=N * (rc["iterations"] + rc["jvps"]) / (c1 - c0), unit="voxel-iters/s", cores=cores,
+                   kind="oracle",
+                   sample=f"{rc['iterations']} map applications of the FP64 oracle (literal 18-transform map, "
+                          f"RPM) on the same {a.n}^3 void cell, {c1 - c0:.1f} s")
+
+    out = {
+        "metric": "voxel-iters/s + time to 1e-6 residual at 128^3 voids; warm-start vs plain RPM",
+        "value": value,
+        "unit": "voxel-iters/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * el / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if a.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{a.n}^3 spherical voids (radii {6 * a.n / 128:g}-{12 * a.n / 128:g} voxels, "
+                               f"vf {w['info']['vf']:.3f}, seed {a.seed}), void stiffness 1e-8, eps_zz 0.01, "
+                               f"plain RPM (no warm start), p_max 32, n_max 10, FP32 fields + FP64 RPM steps",
+                   "voxels": N, "p_end": r["basis_dim"], "jvps": r["jvps"],
+                   "time_to_tol_s": ttt, "time_to_tol_run": ttt_info},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "avg_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per_launch},
+        "kernels": per_kernel,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -122,6 +122,9 @@ typedef struct {
     int32_t decisions_cap;
     double kernel_ms[RPM_NKERNEL];     /* summed HIP-event times (profile = 1)  */
     int32_t kernel_launches[RPM_NKERNEL];
+    double kernel_bytes[RPM_NKERNEL];  /* summed algorithmic HBM bytes of those
+                                          launches: every input read once and
+                                          every output written once (profile=1) */
 } rpm_stats;
 
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value

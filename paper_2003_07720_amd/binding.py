@@ -48,7 +48,8 @@ class RpmStats(ctypes.Structure):
                 ("growth_events", ctypes.c_int32), ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
                 ("decisions", ctypes.POINTER(ctypes.c_int32)), ("decisions_cap", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double * RPM_NKERNEL), ("kernel_launches", ctypes.c_int32 * RPM_NKERNEL)]
+                ("kernel_ms", ctypes.c_double * RPM_NKERNEL), ("kernel_launches", ctypes.c_int32 * RPM_NKERNEL),
+                ("kernel_bytes", ctypes.c_double * RPM_NKERNEL)]
 
 
 _P = ctypes.POINTER
@@ -183,7 +184,8 @@ def _stats_dict(st, hist, dec):
                 history=hist[:min(it, hist.size)].copy() if hist is not None else None,
                 decisions=dec[:min(st.growth_events, dec.size)].copy() if dec is not None else None,
                 kernel_ms={KERNEL_NAMES[k]: st.kernel_ms[k] for k in range(RPM_NKERNEL)},
-                kernel_launches={KERNEL_NAMES[k]: st.kernel_launches[k] for k in range(RPM_NKERNEL)})
+                kernel_launches={KERNEL_NAMES[k]: st.kernel_launches[k] for k in range(RPM_NKERNEL)},
+                kernel_bytes={KERNEL_NAMES[k]: st.kernel_bytes[k] for k in range(RPM_NKERNEL)})
 
 
 def _new_stats(hist_cap):

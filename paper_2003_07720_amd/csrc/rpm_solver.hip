@@ -183,10 +183,12 @@ struct Prof {
     struct Rec {
         hipEvent_t a, b;
         int k;
+        double bytes;
     };
     std::vector<Rec> recs;
     double ms[RPM_NKERNEL] = {0};
     int n[RPM_NKERNEL] = {0};
+    double bytes[RPM_NKERNEL] = {0};
     hipEvent_t get()
     {
         if (!pool.empty()) {
@@ -205,6 +207,7 @@ struct Prof {
             if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
                 ms[r.k] += t;
                 n[r.k] += 1;
+                bytes[r.k] += r.bytes;
             }
             pool.push_back(r.a);
             pool.push_back(r.b);
@@ -217,6 +220,7 @@ struct Prof {
         for (int k = 0; k < RPM_NKERNEL; ++k) {
             ms[k] = 0.0;
             n[k] = 0;
+            bytes[k] = 0.0;
         }
     }
     ~Prof()
@@ -264,13 +268,13 @@ struct Ctx {
         a = prof.get();
         if (a) hipEventRecord(a, s);
     }
-    void mark_end(int k, hipEvent_t a)
+    void mark_end(int k, hipEvent_t a, double bytes = 0.0)
     {
         if (!prof.on || !a) return;
         hipEvent_t b = prof.get();
         if (!b) return;
         hipEventRecord(b, s);
-        prof.recs.push_back({a, b, k});
+        prof.recs.push_back({a, b, k, bytes});
     }
     void check_launch()
     {
@@ -290,31 +294,36 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     cx<T>* S2 = c.template at<cx<T>>(c.L.S2);
     double* pmean = c.template at<double>(c.L.pmean);
     double* perr = c.template at<double>(c.L.perr);
+    // algorithmic bytes of each pass: inputs read once, outputs written once
+    const double fieldB = 6.0 * (double)g.N * sizeof(T);
+    const double specB = 6.0 * (double)g.nspec * sizeof(cx<T>);
+    const double bx = fieldB * (1 + p_corr + (eps_store ? 1 : 0)) + (use_ref ? 0.0 : (double)g.N) + specB;
+    const double bi = specB + fieldB * (2 + p_dots);
     hipEvent_t ev;
     c.mark_begin(RPM_K_XFWD, ev);
     k_xfwd<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d, eps_store,
                                                   c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, g, sh.px,
                                                   c.twx(), done);
-    c.mark_end(RPM_K_XFWD, ev);
+    c.mark_end(RPM_K_XFWD, ev, bx);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YFWD, ev);
         k_yfwd<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
-        c.mark_end(RPM_K_YFWD, ev);
+        c.mark_end(RPM_K_YFWD, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_GAMMA, ev);
     k_gamma<T><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0, dc_mode,
                                                    Edev, pmean, sh.G1, perr, c.st, done);
-    c.mark_end(RPM_K_GAMMA, ev);
+    c.mark_end(RPM_K_GAMMA, ev, 2.0 * specB);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
         k_yinv<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py, c.twy(), done);
-        c.mark_end(RPM_K_YINV, ev);
+        c.mark_end(RPM_K_YINV, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_XINV, ev);
     k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, p_dots ? c.Zc(0) : nullptr,
                                                   p_dots, c.L.ld, p_dots ? c.pdots() : nullptr, g, sh.px, c.twx(),
                                                   done);
-    c.mark_end(RPM_K_XINV, ev);
+    c.mark_end(RPM_K_XINV, ev, bi);
     c.check_launch();
 }
 
@@ -521,6 +530,7 @@ void stats_fill(Ctx<T>& c, rpm_stats* st, const DevState& hs, int jvps, int grow
     for (int k = 0; k < RPM_NKERNEL; ++k) {
         st->kernel_ms[k] = c.prof.ms[k];
         st->kernel_launches[k] = c.prof.n[k];
+        st->kernel_bytes[k] = c.prof.bytes[k];
     }
 }
 

@@ -49,21 +49,21 @@ def rsa_spheres(n, r_min, r_max, vf_target, seed, gap=1.0, max_tries=200000):
     centres, radii = [], []
     tries = 0
     vf = 0.0
+    C = np.zeros((0, 3))
+    Rr = np.zeros(0)
     while vf < vf_target and tries < max_tries:
         tries += 1
         ctr = rng.uniform(0.0, n, size=3)
         rad = rng.uniform(r_min, r_max)
-        ok = True
-        for (c2, r2) in zip(centres, radii):
-            d = ctr - c2
+        if Rr.size:
+            d = C - ctr
             d -= n * np.round(d / n)
-            if np.sqrt((d * d).sum()) < rad + r2 + gap:
-                ok = False
-                break
-        if not ok:
-            continue
+            if np.any(np.sqrt((d * d).sum(axis=1)) < rad + Rr + gap):
+                continue
         centres.append(ctr)
         radii.append(rad)
+        C = np.vstack([C, ctr[None, :]])
+        Rr = np.append(Rr, rad)
         # voxelise with periodic minimum image, on a bounding box only
         lo = np.floor(ctr - rad - 1).astype(int)
         hi = np.ceil(ctr + rad + 1).astype(int)
