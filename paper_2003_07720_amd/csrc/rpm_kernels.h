@@ -400,15 +400,12 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
 }
 
 // ---------------------------------------------------------------------------
-// x-inverse: complex-to-real FFT along x, out = eps - t (OUT_XI) or t
-// (OUT_T), and the FP64 projections sum_x <Z_j, out> and <Z_j, eps>
-// (Frobenius) per block, in chunks of 8 columns.
-// grid: nz * (ny / ty).  part_dots row stride = 2 * ld: [zeta(ld) | z(ld)].
+// x-inverse: complex-to-real FFT along x, out = eps - t (OUT_XI) or t (OUT_T).
+// grid: nz * (ny / ty).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
-                                                   T* __restrict__ out, int out_mode, const T* __restrict__ Z,
-                                                   int p, int ld, double* __restrict__ part_dots, Geo g, Plan px,
+                                                   T* __restrict__ out, int out_mode, Geo g, Plan px,
                                                    const cx<T>* __restrict__ twx, const int* __restrict__ done)
 {
     if (done && *done) return;
@@ -418,7 +415,6 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
     cx<T>* tw = B + ty * ss;
-    double* red = reinterpret_cast<double*>(tw + nx);
     const int nyt = g.ny / ty;
     const int z = blockIdx.x / nyt;
     const int y0 = (blockIdx.x - z * nyt) * ty;
@@ -428,7 +424,6 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
     const T invN = T(1.0 / (double)N);
 
     for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
-    T tv[MV][6];
     for (int q = 0; q < 3; ++q) {
         __syncthreads();
         const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
@@ -449,6 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
         }
         __syncthreads();
         const cx<T>* R = lds_fft<T, +1>(A, B, px, ty, ss, tw);
+        const int ca = 2 * q, cb = 2 * q + 1;
 #pragma unroll
         for (int i = 0; i < MV; ++i) {
             const int v = threadIdx.x + i * kThreads;
@@ -456,64 +452,164 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                 const int r = v / nx;
                 const int x = v - r * nx;
                 const cx<T> val = R[r * ss + x];
-                tv[i][2 * q] = val.x * invN;
-                tv[i][2 * q + 1] = val.y * invN;
-            }
-        }
-    }
-    // epilogue
-    T ev[MV][6], ov[MV][6];
-#pragma unroll
-    for (int i = 0; i < MV; ++i) {
-        const int v = threadIdx.x + i * kThreads;
-        if (v < nvox) {
-            const long long gi = base + v;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                ev[i][c] = eps[c * N + gi];
-                ov[i][c] = (out_mode == OUT_XI) ? (ev[i][c] - tv[i][c]) : tv[i][c];
-                out[c * N + gi] = ov[i][c];
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                ev[i][c] = T(0);
-                ov[i][c] = T(0);
-            }
-        }
-    }
-    if (p == 0 || part_dots == nullptr) return;
-    for (int j0 = 0; j0 < p; j0 += 8) {
-        double acc[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) acc[m] = 0.0;
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            const int j = j0 + jj;
-            if (j < p) {
-                const T* zj = Z + (long long)j * 6 * N + base;
-#pragma unroll
-                for (int i = 0; i < MV; ++i) {
-                    const int v = threadIdx.x + i * kThreads;
-                    if (v < nvox) {
-#pragma unroll
-                        for (int c = 0; c < 6; ++c) {
-                            const double zc = (double)zj[c * N + v] * frob_w(c);
-                            acc[jj] += zc * (double)ov[i][c];
-                            acc[8 + jj] += zc * (double)ev[i][c];
-                        }
-                    }
+                const long long gi = base + v;
+                const T ta = val.x * invN, tb = val.y * invN;
+                if (out_mode == OUT_XI) {
+                    out[ca * N + gi] = eps[ca * N + gi] - ta;
+                    out[cb * N + gi] = eps[cb * N + gi] - tb;
+                } else {
+                    out[ca * N + gi] = ta;
+                    out[cb * N + gi] = tb;
                 }
             }
         }
-        double* tot = red + kWaves * 16;
-        wg_sum_store<16>(acc, tot, red);
-        if (threadIdx.x < 16) {
-            const int m = threadIdx.x;
-            const int j = j0 + (m & 7);
-            if (j < p) part_dots[(long long)blockIdx.x * 2 * ld + (m < 8 ? 0 : ld) + j] = tot[m];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Products with the basis Z (column-major, column j at Z + j * 6N).
+// One lane per column: lane l works on column j = l mod pp (pp = power of two
+// >= p, <= 64) over its own stretch of elements, streaming its column with
+// 16-byte loads; the field values, shared by all columns, are staged once per
+// tile in LDS (weighted by the Frobenius weight) and read as broadcasts.
+//   part[b][j]      = sum_e w(e) Z_j[e] a[e]          (j < p)
+//   part[b][ld + j] = sum_e w(e) Z_j[e] bv[e]         (TWO)
+//   part[b][p]      = sum_e w(e) a[e]^2               (!TWO)
+// w(e) = 1 on the normal components (e < 3N), 2 on the shear ones.
+// Each block covers kCdBlock consecutive elements of the 6N-vector.
+// ---------------------------------------------------------------------------
+constexpr int kCdTile = 2048;
+constexpr int kCdBlock = 8 * kCdTile;
+
+template <typename TZ>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double2;  // 16-byte loads for double columns
+};
+
+template <typename TA, typename TZ, bool TWO>
+__global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, const TA* __restrict__ bv,
+                                                      const TZ* __restrict__ Z, int p, int pp, long long N,
+                                                      double* __restrict__ part, int ld)
+{
+    constexpr int NV = TWO ? 2 : 1;
+    __shared__ double sa[kCdTile];
+    __shared__ double sb[TWO ? kCdTile : 1];
+    __shared__ double red[kWaves * 64 * NV];
+    __shared__ double nred[kWaves];
+    const long long L6 = 6 * N;
+    const long long N3 = 3 * N;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = lane & (pp - 1);
+    const int nsub = 64 / pp;
+    const int sub = lane / pp;
+    const int span = kCdTile / (kWaves * nsub);
+    const int s0 = (wave * nsub + sub) * span;
+    const TZ* zc = Z + (long long)j * L6;
+    double acc_a = 0.0, acc_b = 0.0, nrm = 0.0;
+    const long long b0 = (long long)blockIdx.x * kCdBlock;
+    for (int t = 0; t < kCdBlock / kCdTile; ++t) {
+        const long long e0 = b0 + (long long)t * kCdTile;
+        if (e0 >= L6) break;
+        const int ne = (int)((L6 - e0) < kCdTile ? (L6 - e0) : kCdTile);
+        __syncthreads();
+        for (int i = threadIdx.x; i < kCdTile; i += kThreads) {
+            double va = 0.0, vb = 0.0;
+            if (i < ne) {
+                const long long e = e0 + i;
+                const double w = e < N3 ? 1.0 : 2.0;
+                va = (double)a[e];
+                if (!TWO) nrm += w * va * va;
+                va *= w;
+                if (TWO) vb = w * (double)bv[e];
+            }
+            sa[i] = va;
+            if (TWO) sb[i] = vb;
+        }
+        __syncthreads();
+        if (j < p) {
+            int n_here = ne - s0;
+            n_here = n_here < 0 ? 0 : (n_here > span ? span : n_here);
+            const TZ* zp = zc + e0 + s0;
+            const double* la = sa + s0;
+            const double* lb = sb + (TWO ? s0 : 0);
+            int k = 0;
+            if (((uintptr_t)zp & 15) == 0) {
+                using V = typename Vec4<TZ>::type;
+                constexpr int VW = sizeof(V) / sizeof(TZ);
+                for (; k + 32 <= n_here; k += 32) {
+                    V zz[32 / VW];
+                    const V* zv = reinterpret_cast<const V*>(zp + k);
+#pragma unroll
+                    for (int u = 0; u < 32 / VW; ++u) zz[u] = zv[u];
+                    const TZ* zs = reinterpret_cast<const TZ*>(zz);
+#pragma unroll
+                    for (int u = 0; u < 32; ++u) {
+                        acc_a += (double)zs[u] * la[k + u];
+                        if (TWO) acc_b += (double)zs[u] * lb[k + u];
+                    }
+                }
+            }
+            for (; k < n_here; ++k) {
+                const double zz = (double)zp[k];
+                acc_a += zz * la[k];
+                if (TWO) acc_b += zz * lb[k];
+            }
         }
     }
+    red[(wave * 64 + lane) * NV] = acc_a;
+    if (TWO) red[(wave * 64 + lane) * NV + 1] = acc_b;
+    if (!TWO) {
+        const double s = wave_sum(nrm);
+        if (lane == 0) nred[wave] = s;
+    }
+    __syncthreads();
+    const long long rowst = TWO ? 2LL * ld : (long long)ld;
+    if ((int)threadIdx.x < p) {
+        double ta = 0.0, tb = 0.0;
+        for (int w = 0; w < kWaves; ++w)
+            for (int q = 0; q < nsub; ++q) {
+                const int idx = (w * 64 + q * pp + threadIdx.x) * NV;
+                ta += red[idx];
+                if (TWO) tb += red[idx + 1];
+            }
+        part[(long long)blockIdx.x * rowst + threadIdx.x] = ta;
+        if (TWO) part[(long long)blockIdx.x * rowst + ld + threadIdx.x] = tb;
+    }
+    if (!TWO && threadIdx.x == 0) {
+        double tn = 0.0;
+        for (int w = 0; w < kWaves; ++w) tn += nred[w];
+        part[(long long)blockIdx.x * rowst + p] = tn;
+    }
+}
+
+// v <- v - sum_j coef_j Z_j (coef device, p values); part[b] = <v, v> (Frobenius).
+template <typename TZ>
+__global__ __launch_bounds__(kThreads) void k_axpy_basis(double* __restrict__ v, const TZ* __restrict__ Z, int p,
+                                                         const double* __restrict__ coef, long long N,
+                                                         double* __restrict__ part)
+{
+    __shared__ double red[kWaves + 1];
+    __shared__ double cf[kMaxP];
+    for (int j = threadIdx.x; j < p; j += kThreads) cf[j] = coef[j];
+    __syncthreads();
+    const long long L6 = 6 * N, N3 = 3 * N;
+    double acc[1] = {0.0};
+    const long long e0 = (long long)blockIdx.x * kCdBlock;
+    for (int i = threadIdx.x; i < kCdBlock; i += kThreads) {
+        const long long e = e0 + i;
+        if (e >= L6) break;
+        double t = v[e];
+        for (int j = 0; j < p; ++j) t -= cf[j] * (double)Z[(long long)j * L6 + e];
+        v[e] = t;
+        acc[0] += (e < N3 ? 1.0 : 2.0) * t * t;
+    }
+    wg_sum_store<1>(acc, part + blockIdx.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -558,78 +654,92 @@ __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restri
     if (threadIdx.x == 0) out[j] = tot[0];
 }
 
-// Solve (I - H) y = r with the stored LU factors (row pivots), single thread.
-__device__ void lu_solve(const DevState* st, int p, const double* r, double* y)
-{
-    double b[kMaxP];
-    for (int i = 0; i < p; ++i) b[i] = r[i];
-    for (int i = 0; i < p; ++i) {  // apply the recorded row swaps
-        const int q = st->piv[i];
-        const double t = b[i];
-        b[i] = b[q];
-        b[q] = t;
-    }
-    for (int i = 0; i < p; ++i) {
-        double s = b[i];
-        for (int j = 0; j < i; ++j) s -= st->LU[i * kMaxP + j] * b[j];
-        b[i] = s;
-    }
-    for (int i = p - 1; i >= 0; --i) {
-        double s = b[i];
-        for (int j = i + 1; j < p; ++j) s -= st->LU[i * kMaxP + j] * y[j];
-        y[i] = s / st->LU[i * kMaxP + i];
-    }
-}
-
 // ---------------------------------------------------------------------------
-// finalize (one block): equilibrium error of the iterate that went through F,
+// finalize (one wave): equilibrium error of the iterate that went through F,
 // convergence / divergence / budget tests, and the Newton step on the
-// unstable subspace z' = z + (I - H)^{-1}(zeta - z), giving the recombination
-// coefficients d = z' - zeta for the next xfwd (eps_next = xi + Z d).
+// unstable subspace z' = z + (I - H)^{-1}(zeta - z) with the stored LU
+// factors (row pivots), giving the recombination coefficients d = z' - zeta
+// for the next xfwd (eps_next = xi + Z d).  The triangular solves run one row
+// at a time with the row's dot product spread over the wave.
 // newton_only: skip the error bookkeeping (used after basis growth).
 // ---------------------------------------------------------------------------
-__global__ void k_finalize(DevState* __restrict__ st, const double* __restrict__ sums, int p, int slot,
-                           int two_d, int newton_only, double* __restrict__ hist, int hist_cap)
+__global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, const double* __restrict__ sums,
+                                                 int p, int slot, int two_d, int newton_only,
+                                                 double* __restrict__ hist, int hist_cap)
 {
-    if (st->done) return;
-    if (threadIdx.x != 0) return;
-    if (!newton_only) {
-        const double* s = st->sig_hat0;
-        const double den = two_d ? (s[0] * s[0] + s[1] * s[1] + 2.0 * s[5] * s[5])
-                                 : (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
-                                    2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
-        const double num = sums[0] > 0.0 ? sums[0] : 0.0;
-        const double err = sqrt(num) / sqrt(den);
-        const int it = ++st->iters;
-        if (hist && it - 1 < hist_cap) hist[it - 1] = err;
-        if (it == 1) st->err0 = err;
-        st->err = err;
-        if (!(err == err) || isinf(err) || err > 1e6 * st->err0) {
-            st->status = 2;
-            st->done = 1;
-        } else if (err <= st->tol) {
-            st->status = 0;
-            st->done = 1;
-        } else if (it >= st->max_iter) {
-            st->status = 1;
+    __shared__ int sdone, snow, ssing;
+    __shared__ double r[kMaxP], b[kMaxP], y[kMaxP];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        sdone = st->done;
+        if (!sdone && !newton_only) {
+            const double* s = st->sig_hat0;
+            const double den = two_d ? (s[0] * s[0] + s[1] * s[1] + 2.0 * s[5] * s[5])
+                                     : (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
+                                        2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+            const double num = sums[0] > 0.0 ? sums[0] : 0.0;
+            const double err = sqrt(num) / sqrt(den);
+            const int it = ++st->iters;
+            if (hist && it - 1 < hist_cap) hist[it - 1] = err;
+            if (it == 1) st->err0 = err;
+            st->err = err;
+            if (!(err == err) || isinf(err) || err > 1e6 * st->err0) {
+                st->status = 2;
+                st->done = 1;
+            } else if (err <= st->tol) {
+                st->status = 0;
+                st->done = 1;
+            } else if (it >= st->max_iter) {
+                st->status = 1;
+                st->done = 1;
+            }
+        }
+        snow = st->done;
+        ssing = st->singular;
+    }
+    __syncthreads();
+    if (sdone) return;
+    for (int j = t; j < p; j += 64) {
+        const double ze = sums[1 + j], zz = sums[1 + p + j];
+        st->zeta[j] = ze;
+        st->z[j] = zz;
+        st->zeta_ring[slot][j] = ze;
+        r[j] = ze - zz;
+        b[j] = ze - zz;
+    }
+    __syncthreads();
+    if (snow) return;
+    if (ssing) {
+        if (t == 0) {
+            st->status = 3;
             st->done = 1;
         }
-    }
-    for (int j = 0; j < p; ++j) {
-        st->zeta[j] = sums[1 + j];
-        st->z[j] = sums[1 + p + j];
-        st->zeta_ring[slot][j] = sums[1 + j];
-    }
-    if (st->done) return;
-    if (st->singular) {
-        st->status = 3;
-        st->done = 1;
         return;
     }
-    double r[kMaxP], y[kMaxP];
-    for (int j = 0; j < p; ++j) r[j] = st->zeta[j] - st->z[j];
-    if (p > 0) lu_solve(st, p, r, y);
-    for (int j = 0; j < p; ++j) st->d[j] = y[j] - r[j];  // z' - zeta = (z + y) - zeta
+    if (p == 0) return;
+    if (t == 0)
+        for (int i = 0; i < p; ++i) {
+            const int q = st->piv[i];
+            const double tmp = b[i];
+            b[i] = b[q];
+            b[q] = tmp;
+        }
+    __syncthreads();
+    for (int i = 0; i < p; ++i) {  // unit lower triangle
+        double v = 0.0;
+        for (int j = t; j < i; j += 64) v += st->LU[i * kMaxP + j] * b[j];
+        v = wave_sum(v);
+        if (t == 0) b[i] -= v;
+        __syncthreads();
+    }
+    for (int i = p - 1; i >= 0; --i) {  // upper triangle
+        double v = 0.0;
+        for (int j = i + 1 + t; j < p; j += 64) v += st->LU[i * kMaxP + j] * y[j];
+        v = wave_sum(v);
+        if (t == 0) y[i] = (b[i] - v) / st->LU[i * kMaxP + i];
+        __syncthreads();
+    }
+    for (int j = t; j < p; j += 64) st->d[j] = y[j] - r[j];  // z' - zeta = (z + y) - zeta
 }
 
 // H gains row and column p: H[i][p] = col[i] (i <= p), H[p][j] = row[j] (j < p).
@@ -747,99 +857,6 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(double* __restrict__ y, 
         }
     }
     wg_sum_store<1>(acc, part + blockIdx.x, red);
-}
-
-// Optionally v -= Z coef (coef device, p values, null = no update), then
-// part[b][j] = <Z_j, v> for j < p and part[b][p] = <v, v>.  ld = p + 1.
-template <typename TV, typename TZ>
-__global__ __launch_bounds__(kThreads) void k_dots(TV* __restrict__ v, const TZ* __restrict__ Z, int p,
-                                                   const double* __restrict__ coef, long long N,
-                                                   double* __restrict__ part)
-{
-    __shared__ double red[kWaves * 9 + 9];
-    __shared__ double cf[kMaxP];
-    if (coef)
-        for (int j = threadIdx.x; j < p; j += kThreads) cf[j] = coef[j];
-    __syncthreads();
-    const long long b0 = (long long)blockIdx.x * kChunk;
-    const int ld = p + 1;
-    if (coef) {
-        for (int i = 0; i < kChunk / kThreads; ++i) {
-            const long long x = b0 + threadIdx.x + i * kThreads;
-            if (x >= N) break;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const long long o = c * N + x;
-                double t = (double)v[o];
-                for (int j = 0; j < p; ++j) t -= cf[j] * (double)Z[(long long)j * 6 * N + o];
-                v[o] = (TV)t;
-            }
-        }
-    }
-    for (int j0 = 0; j0 <= p; j0 += 8) {
-        double acc[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) acc[m] = 0.0;
-        for (int i = 0; i < kChunk / kThreads; ++i) {
-            const long long x = b0 + threadIdx.x + i * kThreads;
-            if (x >= N) break;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const long long o = c * N + x;
-                const double vv = (double)v[o] * frob_w(c);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int j = j0 + m;
-                    if (j < p) acc[m] += vv * (double)Z[(long long)j * 6 * N + o];
-                    else if (j == p) acc[m] += vv * (double)v[o];
-                }
-            }
-        }
-        double* tot = red + kWaves * 8;
-        wg_sum_store<8>(acc, tot, red);
-        if (threadIdx.x < 8 && j0 + (int)threadIdx.x <= p)
-            part[(long long)blockIdx.x * ld + j0 + threadIdx.x] = tot[threadIdx.x];
-    }
-}
-
-// part[b][j] = <Z_j, a>, part[b][ld + j] = <Z_j, b> (same layout as xinv).
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_dots2(const T* __restrict__ a, const T* __restrict__ bvec,
-                                                    const T* __restrict__ Z, int p, int ld, long long N,
-                                                    double* __restrict__ part)
-{
-    __shared__ double red[kWaves * 16 + 16];
-    const long long b0 = (long long)blockIdx.x * kChunk;
-    for (int j0 = 0; j0 < p; j0 += 8) {
-        double acc[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) acc[m] = 0.0;
-        for (int i = 0; i < kChunk / kThreads; ++i) {
-            const long long x = b0 + threadIdx.x + i * kThreads;
-            if (x >= N) break;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const long long o = c * N + x;
-                const double av = (double)a[o] * frob_w(c), bv = (double)bvec[o] * frob_w(c);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const int j = j0 + m;
-                    if (j < p) {
-                        const double zz = (double)Z[(long long)j * 6 * N + o];
-                        acc[m] += av * zz;
-                        acc[8 + m] += bv * zz;
-                    }
-                }
-            }
-        }
-        double* tot = red + kWaves * 16;
-        wg_sum_store<16>(acc, tot, red);
-        if (threadIdx.x < 16) {
-            const int m = threadIdx.x;
-            const int j = j0 + (m & 7);
-            if (j < p) part[(long long)blockIdx.x * 2 * ld + (m < 8 ? 0 : ld) + j] = tot[m];
-        }
-    }
 }
 
 template <typename TI, typename TO>

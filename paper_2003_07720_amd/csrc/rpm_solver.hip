@@ -74,7 +74,7 @@ struct Shapes {
     Geo g;
     Plan px, py, pr;
     size_t lds_x, lds_y, lds_g;
-    int G1, Gy, G3, Gg;
+    int G1, Gy, G3, Gg, Gp;
     bool ok;
 };
 
@@ -121,6 +121,7 @@ Shapes<T> make_shapes(const int32_t n[3])
     s.Gy = 6 * g.nh * (g.nz / g.tz);
     s.G3 = (npen + g.np - 1) / g.np;
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
+    s.Gp = (int)((6 * g.N + kCdBlock - 1) / kCdBlock);
     return s;
 }
 
@@ -156,8 +157,8 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.hist = take(sizeof(double) * L.hist_cap);
     L.pmean = take(sizeof(double) * 6 * s.G1);
     L.perr = take(sizeof(double) * s.G3);
-    L.pdots = take(sizeof(double) * 2 * L.ld * std::max(s.G1, s.Gg));
-    L.pg = take(sizeof(double) * (kMaxP + 4) * s.Gg);
+    L.pdots = take(sizeof(double) * 2 * L.ld * std::max(s.G1, s.Gp));
+    L.pg = take(sizeof(double) * (kMaxP + 4) * std::max(s.Gg, s.Gp));
     L.sums = take(sizeof(double) * (2 * kMaxP + 8));
     L.gsum = take(sizeof(double) * (kMaxP + 8));
     for (int i = 0; i < 4; ++i) L.ring[i] = take(fT);
@@ -286,7 +287,7 @@ struct Ctx {
 // by Z d), leaving partial sums for the error and the projections.
 template <typename T>
 void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_inv, T* out, int out_mode,
-           int use_ref, int dc_mode, const double* Edev, int p_dots, const int* done)
+           int use_ref, int dc_mode, const double* Edev, const int* done)
 {
     const Shapes<T>& sh = c.sh;
     const Geo& g = sh.g;
@@ -298,7 +299,7 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     const double fieldB = 6.0 * (double)g.N * sizeof(T);
     const double specB = 6.0 * (double)g.nspec * sizeof(cx<T>);
     const double bx = fieldB * (1 + p_corr + (eps_store ? 1 : 0)) + (use_ref ? 0.0 : (double)g.N) + specB;
-    const double bi = specB + fieldB * (2 + p_dots);
+    const double bi = specB + fieldB * 2;
     hipEvent_t ev;
     c.mark_begin(RPM_K_XFWD, ev);
     k_xfwd<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d, eps_store,
@@ -320,11 +321,35 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         c.mark_end(RPM_K_YINV, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_XINV, ev);
-    k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, p_dots ? c.Zc(0) : nullptr,
-                                                  p_dots, c.L.ld, p_dots ? c.pdots() : nullptr, g, sh.px, c.twx(),
-                                                  done);
+    k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, g, sh.px, c.twx(), done);
     c.mark_end(RPM_K_XINV, ev, bi);
     c.check_launch();
+}
+
+int pow2_cols(int p)
+{
+    int pp = 8;
+    while (pp < p) pp *= 2;
+    return pp;
+}
+
+// Products <Z_j, a> (and <Z_j, b> or <a, a>) for j < p, per block of kCdBlock elements.
+template <typename TA, typename TZ, bool TWO>
+void launch_coldots(hipStream_t s, int G, const TA* a, const TA* b, const TZ* Z, int p, long long N, double* part,
+                    int ld)
+{
+    k_coldots<TA, TZ, TWO><<<G, kThreads, 0, s>>>(a, b, Z, p, pow2_cols(p), N, part, ld);
+}
+
+// zeta_j = <Z_j, xi>, z_j = <Z_j, eps> partial sums for the Newton step.
+template <typename T>
+void project(Ctx<T>& c, const T* xi, const T* eps, int p)
+{
+    if (p == 0) return;
+    hipEvent_t ev;
+    c.mark_begin(RPM_K_PROJECT, ev);
+    launch_coldots<T, T, true>(c.s, c.sh.Gp, xi, eps, c.Zc(0), p, c.sh.g.N, c.pdots(), c.L.ld);
+    c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * (2 + p));
 }
 
 template <typename T>
@@ -336,7 +361,7 @@ void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, int G_dots
                                                    c.sh.G3, c.pdots(), G_dots, c.L.ld, p, c.sums(), done);
     c.mark_end(RPM_K_REDUCE, ev);
     c.mark_begin(RPM_K_FINAL, ev);
-    k_finalize<<<1, 1, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only,
+    k_finalize<<<1, 64, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only,
                                  c.template at<double>(c.L.hist), (int)c.L.hist_cap);
     c.mark_end(RPM_K_FINAL, ev);
     c.check_launch();
@@ -418,7 +443,7 @@ void set_E(Ctx<T>& c, const double E[6])
 template <typename T>
 void project_compatible(Ctx<T>& c, T* v, T* out)
 {
-    run_F<T>(c, v, 0, nullptr, v, out, OUT_T, 1, DC_ZERO, c.st->Ezero, 0, nullptr);
+    run_F<T>(c, v, 0, nullptr, v, out, OUT_T, 1, DC_ZERO, c.st->Ezero, nullptr);
 }
 
 // Basis growth In(q, Z) after main-loop F application number it (Sec. 3:
@@ -471,30 +496,37 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         k_convert<double, T><<<gb, 256, 0, c.s>>>(v, tmp, 1.0 / nrm, nel);
         project_compatible<T>(c, tmp, tmp2);
         k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
-        // two classical Gram-Schmidt passes against Z
+        // two classical Gram-Schmidt passes against Z: coefficients, update, coefficients,
+        // update with the norm of the result
+        const int Gp = c.sh.Gp;
         double* coef = c.gsum();
-        k_dots<double, T><<<Gg, kThreads, 0, c.s>>>(v, c.Zc(0), p, nullptr, N, c.pg());
-        reduce_cols(c, c.pg(), Gg, p + 1, p + 1, coef);
-        k_dots<double, T><<<Gg, kThreads, 0, c.s>>>(v, c.Zc(0), p, coef, N, c.pg());
-        reduce_cols(c, c.pg(), Gg, p + 1, p + 1, c.sums() + kMaxP + 2);
-        k_dots<double, T><<<Gg, kThreads, 0, c.s>>>(v, c.Zc(0), p, c.sums() + kMaxP + 2, N, c.pg());
-        reduce_cols(c, c.pg(), Gg, p + 1, p + 1, coef);
+        double* coef2 = c.sums() + kMaxP + 2;
+        if (p > 0) {
+            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zc(0), p, N, c.pg(), p + 1);
+            reduce_cols(c, c.pg(), Gp, p + 1, p, coef);
+            k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zc(0), p, coef, N, c.pg());
+            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zc(0), p, N, c.pg(), p + 1);
+            reduce_cols(c, c.pg(), Gp, p + 1, p, coef2);
+        }
+        k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zc(0), p, coef2, N, c.pg());
+        reduce_cols(c, c.pg(), Gp, 1, 1, coef + kMaxP);
         double n2;
-        if (!sync_read(c, &n2, coef + p, sizeof(n2))) return -1;
+        if (!sync_read(c, &n2, coef + kMaxP, sizeof(n2))) return -1;
         const double vn = std::sqrt(std::max(n2, 0.0));
         if (!(vn > 1e-10)) continue;
         k_convert<double, T><<<gb, 256, 0, c.s>>>(v, c.Zc(p), 1.0 / vn, nel);
-        // Jacobian-vector product w = F(z_p; E = 0) with the new column of H
-        run_F<T>(c, c.Zc(p), 0, nullptr, c.Zc(p), c.Wc(p), OUT_XI, 0, DC_MEAN, c.st->Ezero, p + 1, nullptr);
-        k_reduce_main<<<1 + 2 * (p + 1), kThreads, 0, c.s>>>(nullptr, 0, c.pdots(), c.sh.G1, c.L.ld, p + 1,
-                                                             c.sums(), nullptr);
+        // Jacobian-vector product w = F(z_p; E = 0): new column <z_i, w> (i <= p) of H
+        run_F<T>(c, c.Zc(p), 0, nullptr, c.Zc(p), c.Wc(p), OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
+        double* hcol = c.sums() + 1;
+        launch_coldots<T, T, false>(c.s, Gp, c.Wc(p), nullptr, c.Zc(0), p + 1, N, c.pg(), p + 2);
+        reduce_cols(c, c.pg(), Gp, p + 2, p + 1, hcol);
         // new row: <z_p, w_j> for j < p
         double* row = c.gsum();
         if (p > 0) {
-            k_dots<T, T><<<Gg, kThreads, 0, c.s>>>(c.Zc(p), c.Wc(0), p, nullptr, N, c.pg());
-            reduce_cols(c, c.pg(), Gg, p + 1, p, row);
+            launch_coldots<T, T, false>(c.s, Gp, c.Zc(p), nullptr, c.Wc(0), p, N, c.pg(), p + 1);
+            reduce_cols(c, c.pg(), Gp, p + 1, p, row);
         }
-        k_border<<<1, 1, 0, c.s>>>(c.st, c.sums() + 1, row, p);
+        k_border<<<1, 1, 0, c.s>>>(c.st, hcol, row, p);
         ++p;
         ++added;
         ++*jvps;
@@ -558,8 +590,9 @@ rpm_status solve_impl(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
         const long long nel = 6 * N;
         k_fill_uniform<T><<<(int)((nel + 255) / 256), 256, 0, c.s>>>(c.eps(), c.st->E, N);
     }
-    run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(1), OUT_XI, 0, DC_MEAN, c.st->E, rpm ? p : 0, done);
-    reduce_and_finalize(c, rpm ? p : 0, 1, 0, c.sh.G1, done);
+    run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(1), OUT_XI, 0, DC_MEAN, c.st->E, done);
+    if (rpm) project(c, c.ring(1), c.eps(), p);
+    reduce_and_finalize(c, rpm ? p : 0, 1, 0, c.sh.Gp, done);
 
     int it = 1, nu = 0, nq = 0;
     int hdone = 0;
@@ -580,19 +613,20 @@ rpm_status solve_impl(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
                 nu = 0;
                 nq = 0;
                 // projections of the current pair (eps, xi) on the grown basis, Newton step
-                k_dots2<T><<<c.sh.Gg, kThreads, 0, c.s>>>(c.ring(it), c.eps(), c.Zc(0), p, c.L.ld, N, c.pdots());
-                reduce_and_finalize(c, p, it, 1, c.sh.Gg, done);
+                project(c, c.ring(it), c.eps(), p);
+                reduce_and_finalize(c, p, it, 1, c.sh.Gp, done);
             }
         }
         // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step
         ++it;
         const T* xprev = c.ring(it - 1);
         if (rpm) {
-            run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, p, done);
+            run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done);
+            project(c, c.ring(it), c.eps(), p);
         } else {
-            run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, 0, done);
+            run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done);
         }
-        reduce_and_finalize(c, rpm ? p : 0, it, 0, c.sh.G1, done);
+        reduce_and_finalize(c, rpm ? p : 0, it, 0, c.sh.Gp, done);
         ++nu;
         ++nq;
     }
@@ -695,8 +729,8 @@ rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_optio
     rs = prepare(c, pr, o, false, &p);
     if (rs != RPM_OK) return rs;
     set_E(c, E);
-    run_F<T>(c, (const T*)eps, 0, nullptr, (const T*)eps, (T*)xi, OUT_XI, 0, DC_MEAN, c.st->E, 0, nullptr);
-    reduce_and_finalize(c, 0, 1, 0, c.sh.G1, nullptr);
+    run_F<T>(c, (const T*)eps, 0, nullptr, (const T*)eps, (T*)xi, OUT_XI, 0, DC_MEAN, c.st->E, nullptr);
+    reduce_and_finalize(c, 0, 1, 0, c.sh.Gp, nullptr);
     DevState hs;
     if (!sync_read(c, &hs, c.st, sizeof(hs))) return RPM_E_HIP;
     if (err) *err = hs.err;
