@@ -64,6 +64,18 @@ constexpr int kStateMagic = 0x52504d31;
 enum { DC_MEAN = 0, DC_ZERO = 1 };   // t_hat(0) = N(<eps> - E) or 0
 enum { OUT_XI = 0, OUT_T = 1 };      // xinv writes eps - t or t
 
+// 16-byte vector type of an element type
+template <typename TZ>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using type = float4;
+};
+template <>
+struct Vec4<double> {
+    using type = double2;  // 16-byte loads for double columns
+};
+
 template <typename T>
 struct MaxV;
 template <>
@@ -75,7 +87,7 @@ struct MaxV<double> { static constexpr int v = 4; };
 // x-forward: recombination + constitutive law + R2C FFT along x.
 // grid: nz * (ny / ty) blocks.  LDS: 2 * ty * (nx+1) + nx complex + reduction.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const T* __restrict__ Z, int p,
                                                    const double* __restrict__ dco, T* __restrict__ eps_out,
                                                    const uint8_t* __restrict__ phase, const double* __restrict__ lame,
@@ -101,44 +113,80 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
 
     for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
 
+    // VEC: each thread takes runs of VL consecutive voxels (16-byte accesses)
+    constexpr int VL = VEC ? (int)(16 / sizeof(T)) : 1;
+    using V = typename Vec4<T>::type;
     T sig[MV][6];
     double msum[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < MV; ++i) {
-        const int v = threadIdx.x + i * kThreads;
-        if (v < nvox) {
-            const long long gi = base + v;
-            T e[6];
+    for (int i = 0; i < MV / VL; ++i) {
+        const int v0 = (threadIdx.x + i * kThreads) * VL;
+        if (v0 < nvox) {
+            const long long gi = base + v0;
+            T e[VL][6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) e[c] = xin[c * N + gi];
+            for (int c = 0; c < 6; ++c) {
+                if constexpr (VEC) {
+                    const V t = *reinterpret_cast<const V*>(xin + c * N + gi);
+                    const T* ts = reinterpret_cast<const T*>(&t);
+#pragma unroll
+                    for (int u = 0; u < VL; ++u) e[u][c] = ts[u];
+                } else {
+                    e[0][c] = xin[c * N + gi];
+                }
+            }
             for (int j = 0; j < p; ++j) {
                 const T dj = (T)dco[j];
                 const T* zj = Z + (long long)j * 6 * N + gi;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) e[c] += dj * zj[c * N];
+                for (int c = 0; c < 6; ++c) {
+                    if constexpr (VEC) {
+                        const V t = *reinterpret_cast<const V*>(zj + c * N);
+                        const T* ts = reinterpret_cast<const T*>(&t);
+#pragma unroll
+                        for (int u = 0; u < VL; ++u) e[u][c] += dj * ts[u];
+                    } else {
+                        e[0][c] += dj * zj[c * N];
+                    }
+                }
             }
             if (eps_out) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) eps_out[c * N + gi] = e[c];
+                for (int c = 0; c < 6; ++c) {
+                    if constexpr (VEC) {
+                        V t;
+                        T* ts = reinterpret_cast<T*>(&t);
+#pragma unroll
+                        for (int u = 0; u < VL; ++u) ts[u] = e[u][c];
+                        *reinterpret_cast<V*>(eps_out + c * N + gi) = t;
+                    } else {
+                        eps_out[c * N + gi] = e[0][c];
+                    }
+                }
             }
 #pragma unroll
-            for (int c = 0; c < 6; ++c) msum[c] += (double)e[c];
-            T lam, mu;
-            if (use_ref) {
-                lam = (T)lam0;
-                mu = (T)mu0;
-            } else {
-                const int ph = phase[gi];
-                lam = (T)lame[2 * ph];
-                mu = (T)lame[2 * ph + 1];
-            }
-            const T ltr = lam * (e[0] + e[1] + e[2]);
-            const T m2 = mu + mu;
+            for (int u = 0; u < VL; ++u) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) sig[i][c] = m2 * e[c] + (c < 3 ? ltr : T(0));
+                for (int c = 0; c < 6; ++c) msum[c] += (double)e[u][c];
+                T lam, mu;
+                if (use_ref) {
+                    lam = (T)lam0;
+                    mu = (T)mu0;
+                } else {
+                    const int ph = phase[gi + u];
+                    lam = (T)lame[2 * ph];
+                    mu = (T)lame[2 * ph + 1];
+                }
+                const T ltr = lam * (e[u][0] + e[u][1] + e[u][2]);
+                const T m2 = mu + mu;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sig[i * VL + u][c] = m2 * e[u][c] + (c < 3 ? ltr : T(0));
+            }
         } else {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) sig[i][c] = T(0);
+            for (int u = 0; u < VL; ++u)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sig[i * VL + u][c] = T(0);
         }
     }
     if (part_mean) wg_sum_store<6>(msum, part_mean + (long long)blockIdx.x * 6, red);
@@ -147,12 +195,13 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
     for (int q = 0; q < 3; ++q) {
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < MV; ++i) {
-            const int v = threadIdx.x + i * kThreads;
-            if (v < nvox) {
-                const int r = v / nx;
-                const int x = v - r * nx;
-                A[r * ss + x] = cx<T>{sig[i][2 * q], sig[i][2 * q + 1]};
+        for (int i = 0; i < MV / VL; ++i) {
+            const int v0 = (threadIdx.x + i * kThreads) * VL;
+            if (v0 < nvox) {
+                const int r = v0 / nx;
+                const int x = v0 - r * nx;
+#pragma unroll
+                for (int u = 0; u < VL; ++u) A[r * ss + x + u] = cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]};
             }
         }
         __syncthreads();
@@ -481,17 +530,6 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
 constexpr int kCdTile = 2048;
 constexpr int kCdBlock = 8 * kCdTile;
 
-template <typename TZ>
-struct Vec4;
-template <>
-struct Vec4<float> {
-    using type = float4;
-};
-template <>
-struct Vec4<double> {
-    using type = double2;  // 16-byte loads for double columns
-};
-
 template <typename TA, typename TZ, bool TWO>
 __global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, const TA* __restrict__ bv,
                                                       const TZ* __restrict__ Z, int p, int pp, long long N,
@@ -717,6 +755,10 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
         return;
     }
     if (p == 0) return;
+    // stage the factors in LDS (row stride kMaxP + 1) before the dependent row sweeps
+    __shared__ double LUs[kMaxP * (kMaxP + 1)];
+    for (int i = 0; i < p; ++i)
+        for (int j = t; j < p; j += 64) LUs[i * (kMaxP + 1) + j] = st->LU[i * kMaxP + j];
     if (t == 0)
         for (int i = 0; i < p; ++i) {
             const int q = st->piv[i];
@@ -727,16 +769,16 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
     __syncthreads();
     for (int i = 0; i < p; ++i) {  // unit lower triangle
         double v = 0.0;
-        for (int j = t; j < i; j += 64) v += st->LU[i * kMaxP + j] * b[j];
+        for (int j = t; j < i; j += 64) v += LUs[i * (kMaxP + 1) + j] * b[j];
         v = wave_sum(v);
         if (t == 0) b[i] -= v;
         __syncthreads();
     }
     for (int i = p - 1; i >= 0; --i) {  // upper triangle
         double v = 0.0;
-        for (int j = i + 1 + t; j < p; j += 64) v += st->LU[i * kMaxP + j] * y[j];
+        for (int j = i + 1 + t; j < p; j += 64) v += LUs[i * (kMaxP + 1) + j] * y[j];
         v = wave_sum(v);
-        if (t == 0) y[i] = (b[i] - v) / st->LU[i * kMaxP + i];
+        if (t == 0) y[i] = (b[i] - v) / LUs[i * (kMaxP + 1) + i];
         __syncthreads();
     }
     for (int j = t; j < p; j += 64) st->d[j] = y[j] - r[j];  // z' - zeta = (z + y) - zeta
@@ -751,41 +793,63 @@ __global__ void k_border(DevState* __restrict__ st, const double* __restrict__ c
     for (int j = 0; j < p; ++j) st->H[p * kMaxP + j] = row[j];
 }
 
-// LU factorisation with partial pivoting of I - H (one thread).
-__global__ void k_factor(DevState* __restrict__ st, int p)
+// LU factorisation with partial pivoting of I - H, one wave of 64 threads on
+// an LDS copy (row stride kMaxP + 1 keeps the row-parallel updates free of
+// bank conflicts).  Thread t eliminates row c + 1 + t at step c.
+__global__ __launch_bounds__(64) void k_factor(DevState* __restrict__ st, int p)
 {
-    if (threadIdx.x != 0) return;
+    constexpr int LD = kMaxP + 1;
+    __shared__ double A[kMaxP * LD];
+    __shared__ double amax_s;
+    __shared__ int piv_s, sing_s;
+    const int t = threadIdx.x;
     double amax = 0.0;
     for (int i = 0; i < p; ++i)
-        for (int j = 0; j < p; ++j) {
+        for (int j = t; j < p; j += 64) {
             const double a = (i == j ? 1.0 : 0.0) - st->H[i * kMaxP + j];
-            st->LU[i * kMaxP + j] = a;
+            A[i * LD + j] = a;
             amax = fmax(amax, fabs(a));
         }
-    int sing = 0;
-    for (int c = 0; c < p; ++c) {
-        int q = c;
-        for (int r = c + 1; r < p; ++r)
-            if (fabs(st->LU[r * kMaxP + c]) > fabs(st->LU[q * kMaxP + c])) q = r;
-        st->piv[c] = q;
-        if (!(fabs(st->LU[q * kMaxP + c]) > 1e-14 * amax)) {
-            sing = 1;
-            break;
-        }
-        if (q != c)
-            for (int j = 0; j < p; ++j) {
-                const double t = st->LU[c * kMaxP + j];
-                st->LU[c * kMaxP + j] = st->LU[q * kMaxP + j];
-                st->LU[q * kMaxP + j] = t;
-            }
-        for (int r = c + 1; r < p; ++r) {
-            const double f = st->LU[r * kMaxP + c] / st->LU[c * kMaxP + c];
-            st->LU[r * kMaxP + c] = f;
-            for (int j = c + 1; j < p; ++j) st->LU[r * kMaxP + j] -= f * st->LU[c * kMaxP + j];
-        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (t == 0) {
+        amax_s = amax;
+        sing_s = 0;
     }
-    st->singular = sing;
-    st->p = p;
+    __syncthreads();
+    for (int c = 0; c < p; ++c) {
+        if (t == 0) {
+            int q = c;
+            for (int r = c + 1; r < p; ++r)
+                if (fabs(A[r * LD + c]) > fabs(A[q * LD + c])) q = r;
+            piv_s = q;
+            st->piv[c] = q;
+            if (!(fabs(A[q * LD + c]) > 1e-14 * amax_s)) sing_s = 1;
+        }
+        __syncthreads();
+        if (sing_s) break;
+        const int q = piv_s;
+        if (q != c)
+            for (int j = t; j < p; j += 64) {
+                const double tmp = A[c * LD + j];
+                A[c * LD + j] = A[q * LD + j];
+                A[q * LD + j] = tmp;
+            }
+        __syncthreads();
+        const int r = c + 1 + t;
+        if (r < p) {
+            const double f = A[r * LD + c] / A[c * LD + c];
+            A[r * LD + c] = f;
+            for (int j = c + 1; j < p; ++j) A[r * LD + j] -= f * A[c * LD + j];
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < p; ++i)
+        for (int j = t; j < p; j += 64) st->LU[i * kMaxP + j] = A[i * LD + j];
+    if (t == 0) {
+        st->singular = sing_s;
+        st->p = p;
+    }
 }
 
 // ---------------------------------------------------------------------------

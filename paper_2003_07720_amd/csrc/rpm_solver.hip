@@ -302,9 +302,14 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     const double bi = specB + fieldB * 2;
     hipEvent_t ev;
     c.mark_begin(RPM_K_XFWD, ev);
-    k_xfwd<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d, eps_store,
-                                                  c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, g, sh.px,
-                                                  c.twx(), done);
+    if (g.nx % (16 / (int)sizeof(T)) == 0)
+        k_xfwd<T, true><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d,
+                                                            eps_store, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1,
+                                                            pmean, g, sh.px, c.twx(), done);
+    else
+        k_xfwd<T, false><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d,
+                                                             eps_store, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1,
+                                                             pmean, g, sh.px, c.twx(), done);
     c.mark_end(RPM_K_XFWD, ev, bx);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YFWD, ev);
@@ -531,7 +536,7 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         ++added;
         ++*jvps;
     }
-    if (added > 0) k_factor<<<1, 1, 0, c.s>>>(c.st, p);
+    if (added > 0) k_factor<<<1, 64, 0, c.s>>>(c.st, p);
     c.mark_end(RPM_K_GROWTH, ev);
     c.check_launch();
     return added;
