@@ -34,7 +34,9 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--seed", type=int, default=3000)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--ttt-iters", type=int, default=4000, help="iteration cap of the time-to-tolerance solve")
+    ap.add_argument("--ttt-iters", type=int, default=4000, help="iteration cap of the time-to-tolerance solves")
+    ap.add_argument("--ttt-loose", default="1e-2,3e-3",
+                    help="looser tolerances timed for RPM and the basic scheme (comma list, '' = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle map applications in the CPU sample")
@@ -113,6 +115,20 @@ def main():
         if r2["status"] == "RPM_OK":
             ttt = s1 - s0
         print(f"bench: time-to-tol solve {ttt_info}", file=sys.stderr, flush=True)
+        # looser tolerances: plain RPM against the basic scheme (Algorithm 1), each timed
+        loose = {}
+        for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
+            for scheme in ("rpm", "basic"):
+                o3 = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, scheme=scheme, refine=0))
+                torch.cuda.synchronize()
+                u0 = time.perf_counter()
+                r3 = B.fft_solve(phase, lt, l0, E, o3, workspace=ws, want_eps=False)
+                torch.cuda.synchronize()
+                u1 = time.perf_counter()
+                loose[f"{scheme}@{tl:g}"] = dict(status=r3["status"], iterations=r3["iterations"],
+                                                 seconds=round(u1 - u0, 4), residual=r3["residual"])
+        ttt_info["looser_tolerances"] = loose
+        print(f"bench: looser tolerances {loose}", file=sys.stderr, flush=True)
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None

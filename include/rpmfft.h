@@ -108,6 +108,16 @@ typedef struct {
                                  or 2) at each growth event, in order            */
     int32_t replay_len;
     int32_t profile;          /* record per-kernel-class times with HIP events */
+    int32_t refine;           /* RPM_FP32 only: at most this many FP64
+                                 refinement sweeps (0 = certify only).  With
+                                 refine > 0 the FP32 stage stops at
+                                 max(tol, 1e-5); while the FP64 evaluation of
+                                 the field misses tol, delta = F_u delta + g is
+                                 solved in FP32 (g = FP64 fixed-point residual,
+                                 basis reused) and added to an FP64 iterate;
+                                 the status then reflects the FP64 error       */
+    double refine_tol;        /* correction solves stop at |G(d) - d| <=
+                                 refine_tol |g| (0 < refine_tol < 1)           */
 } rpm_options;
 
 typedef struct {
@@ -126,10 +136,15 @@ typedef struct {
     double kernel_bytes[RPM_NKERNEL];  /* summed algorithmic HBM bytes of those
                                           launches: every input read once and
                                           every output written once (profile=1) */
+    double residual_fp64;     /* equilibrium error evaluated in FP64 of the FP64
+                                 field behind the outputs (RPM_FP32: after
+                                 refinement; RPM_FP64: equals residual)          */
+    int32_t refinements;      /* refinement sweeps performed                      */
 } rpm_stats;
 
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
- * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16. */
+ * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
+ * refine 4, refine_tol 1e-3. */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and
@@ -151,7 +166,10 @@ rpm_status rpm_fft_apply(const rpm_problem *pr, const double E[6], const rpm_opt
 
 /*
  * Solve the cell problem for the mean strain E (Sec. 2) with Algorithm 1 or
- * Algorithm 2 until the equilibrium error of the iterate is <= tol.
+ * Algorithm 2 until the equilibrium error of the iterate is <= tol.  With
+ * RPM_FP32 the converged field is re-evaluated in FP64 (certification) and,
+ * if needed, refined (rpm_options.refine); sig_avg then comes from the FP64
+ * field and eps_out is that field rounded to float.
  *   eps0     DEVICE nullable: starting strain (its mean is replaced by E by
  *            the first application of F); NULL starts from the uniform E.
  *   eps_out  DEVICE nullable: the iterate whose error met tol (the input of

@@ -40,7 +40,7 @@ class RpmOptions(ctypes.Structure):
                 ("p_max", ctypes.c_int32), ("kappa", ctypes.c_double), ("scheme", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reuse_basis", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("replay", ctypes.POINTER(ctypes.c_int32)), ("replay_len", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
 
 
 class RpmStats(ctypes.Structure):
@@ -49,7 +49,8 @@ class RpmStats(ctypes.Structure):
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int32),
                 ("decisions", ctypes.POINTER(ctypes.c_int32)), ("decisions_cap", ctypes.c_int32),
                 ("kernel_ms", ctypes.c_double * RPM_NKERNEL), ("kernel_launches", ctypes.c_int32 * RPM_NKERNEL),
-                ("kernel_bytes", ctypes.c_double * RPM_NKERNEL)]
+                ("kernel_bytes", ctypes.c_double * RPM_NKERNEL), ("residual_fp64", ctypes.c_double),
+                ("refinements", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -180,7 +181,8 @@ def fft_apply(phase, lame_tab, lame0, E, eps, opts=None, workspace=None):
 def _stats_dict(st, hist, dec):
     it = st.iterations
     return dict(iterations=it, jvps=st.jvps, basis_dim=st.basis_dim, growth_events=st.growth_events,
-                residual=st.residual, seconds=st.seconds,
+                residual=st.residual, residual_fp64=st.residual_fp64, refinements=st.refinements,
+                seconds=st.seconds,
                 history=hist[:min(it, hist.size)].copy() if hist is not None else None,
                 decisions=dec[:min(st.growth_events, dec.size)].copy() if dec is not None else None,
                 kernel_ms={KERNEL_NAMES[k]: st.kernel_ms[k] for k in range(RPM_NKERNEL)},

@@ -52,6 +52,7 @@ struct DevState {
     double mean_eps[6];
     double E[6];       // prescribed mean strain of the current solve
     double Ezero[6];   // zeros (mean strain of Jacobian-vector products)
+    double gnorm;      // norm of the shift field of a correction solve
     double z[kMaxP], zeta[kMaxP], d[kMaxP];
     double zeta_ring[4][kMaxP];
     double H[kMaxP * kMaxP];
@@ -454,7 +455,8 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
-                                                   T* __restrict__ out, int out_mode, Geo g, Plan px,
+                                                   T* __restrict__ out, int out_mode, const T* __restrict__ shift,
+                                                   double* __restrict__ part_inc, Geo g, Plan px,
                                                    const cx<T>* __restrict__ twx, const int* __restrict__ done)
 {
     if (done && *done) return;
@@ -473,6 +475,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
     const T invN = T(1.0 / (double)N);
 
     for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
+    double inc = 0.0;  // sum of w (out - eps)^2 over the tile (correction solves)
     for (int q = 0; q < 3; ++q) {
         __syncthreads();
         const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
@@ -504,14 +507,30 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                 const long long gi = base + v;
                 const T ta = val.x * invN, tb = val.y * invN;
                 if (out_mode == OUT_XI) {
-                    out[ca * N + gi] = eps[ca * N + gi] - ta;
-                    out[cb * N + gi] = eps[cb * N + gi] - tb;
+                    const T ea = eps[ca * N + gi], eb = eps[cb * N + gi];
+                    T oa = ea - ta, ob = eb - tb;
+                    if (shift) {
+                        oa += shift[ca * N + gi];
+                        ob += shift[cb * N + gi];
+                    }
+                    out[ca * N + gi] = oa;
+                    out[cb * N + gi] = ob;
+                    if (part_inc) {
+                        const double da = (double)oa - (double)ea, db = (double)ob - (double)eb;
+                        inc += frob_w(ca) * da * da + frob_w(cb) * db * db;
+                    }
                 } else {
                     out[ca * N + gi] = ta;
                     out[cb * N + gi] = tb;
                 }
             }
         }
+    }
+    if (part_inc) {
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(tw + nx);
+        double v[1] = {inc};
+        wg_sum_store<1>(v, part_inc + blockIdx.x, red);
     }
 }
 
@@ -702,7 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restri
 // newton_only: skip the error bookkeeping (used after basis growth).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, const double* __restrict__ sums,
-                                                 int p, int slot, int two_d, int newton_only,
+                                                 int p, int slot, int two_d, int newton_only, int err_mode,
                                                  double* __restrict__ hist, int hist_cap)
 {
     __shared__ int sdone, snow, ssing;
@@ -716,7 +735,9 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
                                      : (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
                                         2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
             const double num = sums[0] > 0.0 ? sums[0] : 0.0;
-            const double err = sqrt(num) / sqrt(den);
+            // err_mode 0: equilibrium error of the iterate; 1: fixed-point increment
+            // |G(d) - d| / |g| of a correction solve
+            const double err = err_mode == 0 ? sqrt(num) / sqrt(den) : sqrt(num) / st->gnorm;
             const int it = ++st->iters;
             if (hist && it - 1 < hist_cap) hist[it - 1] = err;
             if (it == 1) st->err0 = err;
@@ -782,6 +803,16 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
         __syncthreads();
     }
     for (int j = t; j < p; j += 64) st->d[j] = y[j] - r[j];  // z' - zeta = (z + y) - zeta
+}
+
+// Clear the stop flags and the step counter (a fresh map evaluation).
+__global__ void k_reset_state(DevState* __restrict__ st)
+{
+    if (threadIdx.x == 0) {
+        st->done = 0;
+        st->status = 1;
+        st->iters = 0;
+    }
 }
 
 // H gains row and column p: H[i][p] = col[i] (i <= p), H[p][j] = row[j] (j < p).
@@ -928,6 +959,34 @@ __global__ void k_convert(const TI* __restrict__ in, TO* __restrict__ out, doubl
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (TO)((double)in[i] * scale);
+}
+
+// Refinement helpers: g = xi - eps in the working precision of the correction
+// solve with part[b] = <xi - eps, xi - eps> (FP64); eps64 += d.
+template <typename TG>
+__global__ __launch_bounds__(kThreads) void k_residual_shift(const double* __restrict__ xi,
+                                                             const double* __restrict__ eps, TG* __restrict__ g,
+                                                             long long N, double* __restrict__ part)
+{
+    __shared__ double red[kWaves + 1];
+    double acc[1] = {0.0};
+    const long long L6 = 6 * N, N3 = 3 * N;
+    const long long e0 = (long long)blockIdx.x * kCdBlock;
+    for (int i = threadIdx.x; i < kCdBlock; i += kThreads) {
+        const long long e = e0 + i;
+        if (e >= L6) break;
+        const double d = xi[e] - eps[e];
+        g[e] = (TG)d;
+        acc[0] += (e < N3 ? 1.0 : 2.0) * d * d;
+    }
+    wg_sum_store<1>(acc, part + blockIdx.x, red);
+}
+
+template <typename TD>
+__global__ void k_add_correction(double* __restrict__ eps, const TD* __restrict__ d, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) eps[i] += (double)d[i];
 }
 
 template <typename T>

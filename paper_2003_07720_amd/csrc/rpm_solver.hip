@@ -26,6 +26,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kLdsCap = 60 * 1024;  // leaves room for static shared arrays
 constexpr int kMaxN = 512;
+constexpr double kFp32Stage = 1e-5;  // FP32 stage target before FP64 refinement
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -126,11 +127,27 @@ Shapes<T> make_shapes(const int32_t n[3])
 }
 
 struct Layout {
-    size_t st, twx, twy, twr, lame, hist, pmean, perr, pdots, pg, sums, gsum, ring[4], eps, tmp, tmp2, S1, S2, Z,
-        W, D1, D0, total;
+    size_t st, twx, twy, twr, lame, hist, pmean, perr, pinc, pdots, pg, sums, gsum, ring[4], eps, tmp, tmp2, S1, S2,
+        Z, W, D1, D0, shift, sub64, total;
     int ld;
     long long hist_cap;
 };
+
+rpm_options basic_fp64_options(const rpm_options* o)
+{
+    rpm_options b = *o;
+    b.scheme = RPM_SCHEME_BASIC;
+    b.p_max = 0;
+    b.max_iter = 1;
+    b.precision = RPM_FP64;
+    return b;
+}
+
+template <typename T>
+Shapes<T> make_shapes(const int32_t n[3]);
+
+template <typename T>
+Layout make_layout(const Shapes<T>& s, const rpm_options* o);
 
 template <typename T>
 Layout make_layout(const Shapes<T>& s, const rpm_options* o)
@@ -157,6 +174,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.hist = take(sizeof(double) * L.hist_cap);
     L.pmean = take(sizeof(double) * 6 * s.G1);
     L.perr = take(sizeof(double) * s.G3);
+    L.pinc = take(sizeof(double) * s.G1);
     L.pdots = take(sizeof(double) * 2 * L.ld * std::max(s.G1, s.Gp));
     L.pg = take(sizeof(double) * (kMaxP + 4) * std::max(s.Gg, s.Gp));
     L.sums = take(sizeof(double) * (2 * kMaxP + 8));
@@ -171,6 +189,16 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.W = take(fT * pmax);
     L.D1 = take(pmax > 0 ? fD : 0);
     L.D0 = take(pmax > 0 ? fD : 0);
+    // FP32 fields: shift field of the correction solves and an FP64 pipeline
+    // for certification and refinement
+    const bool fp32 = sizeof(T) == 4;
+    L.shift = take(fp32 ? fT : 0);
+    L.sub64 = off;
+    if (fp32) {
+        const int32_t n[3] = {g.nx, g.ny, g.nz};
+        const rpm_options b = basic_fp64_options(o);
+        off = align_up(off + make_layout<double>(make_shapes<double>(n), &b).total);
+    }
     L.total = off;
     return L;
 }
@@ -287,7 +315,8 @@ struct Ctx {
 // by Z d), leaving partial sums for the error and the projections.
 template <typename T>
 void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_inv, T* out, int out_mode,
-           int use_ref, int dc_mode, const double* Edev, const int* done)
+           int use_ref, int dc_mode, const double* Edev, const int* done, const T* shift = nullptr,
+           double* part_inc = nullptr)
 {
     const Shapes<T>& sh = c.sh;
     const Geo& g = sh.g;
@@ -299,7 +328,7 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     const double fieldB = 6.0 * (double)g.N * sizeof(T);
     const double specB = 6.0 * (double)g.nspec * sizeof(cx<T>);
     const double bx = fieldB * (1 + p_corr + (eps_store ? 1 : 0)) + (use_ref ? 0.0 : (double)g.N) + specB;
-    const double bi = specB + fieldB * 2;
+    const double bi = specB + fieldB * (2 + (shift ? 1 : 0));
     hipEvent_t ev;
     c.mark_begin(RPM_K_XFWD, ev);
     if (g.nx % (16 / (int)sizeof(T)) == 0)
@@ -326,7 +355,8 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         c.mark_end(RPM_K_YINV, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_XINV, ev);
-    k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, g, sh.px, c.twx(), done);
+    k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,
+                                                  c.twx(), done);
     c.mark_end(RPM_K_XINV, ev, bi);
     c.check_launch();
 }
@@ -358,15 +388,19 @@ void project(Ctx<T>& c, const T* xi, const T* eps, int p)
 }
 
 template <typename T>
-void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, int G_dots, const int* done)
+void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, int G_dots, const int* done,
+                         int err_mode = 0)
 {
     hipEvent_t ev;
     c.mark_begin(RPM_K_REDUCE, ev);
-    k_reduce_main<<<1 + 2 * p, kThreads, 0, c.s>>>(newton_only ? nullptr : c.template at<double>(c.L.perr),
-                                                   c.sh.G3, c.pdots(), G_dots, c.L.ld, p, c.sums(), done);
+    const double* perr = newton_only ? nullptr
+                                     : (err_mode == 0 ? c.template at<double>(c.L.perr)
+                                                      : c.template at<double>(c.L.pinc));
+    k_reduce_main<<<1 + 2 * p, kThreads, 0, c.s>>>(perr, err_mode == 0 ? c.sh.G3 : c.sh.G1, c.pdots(), G_dots,
+                                                   c.L.ld, p, c.sums(), done);
     c.mark_end(RPM_K_REDUCE, ev);
     c.mark_begin(RPM_K_FINAL, ev);
-    k_finalize<<<1, 64, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only,
+    k_finalize<<<1, 64, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only, err_mode,
                                  c.template at<double>(c.L.hist), (int)c.L.hist_cap);
     c.mark_end(RPM_K_FINAL, ev);
     c.check_launch();
@@ -389,7 +423,8 @@ void reduce_cols(Ctx<T>& c, const double* part, int G, int ld, int m, double* ou
 
 // Initialise or re-validate the workspace header; uploads the tables.
 template <typename T>
-rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool want_reuse, int* p_io)
+rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool want_reuse, int* p_io,
+                   double tol, double gnorm = 1.0)
 {
     const Geo& g = c.sh.g;
     DevState hs;
@@ -407,7 +442,8 @@ rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool 
     hs.status = 1;
     hs.iters = 0;
     hs.max_iter = o->max_iter;
-    hs.tol = o->tol;
+    hs.tol = tol;
+    hs.gnorm = gnorm;
     hs.err0 = 0.0;
     hs.err = 0.0;
     for (int i = 0; i < 6; ++i) hs.Ezero[i] = 0.0;
@@ -553,14 +589,6 @@ void stats_fill(Ctx<T>& c, rpm_stats* st, const DevState& hs, int jvps, int grow
     st->growth_events = growth;
     st->residual = hs.err;
     st->seconds = secs;
-    if (st->history && st->history_cap > 0) {
-        const int n = std::min(st->history_cap, hs.iters);
-        if (n > 0) {
-            hipMemcpyAsync(st->history, c.template at<double>(c.L.hist), sizeof(double) * n, hipMemcpyDeviceToHost,
-                           c.s);
-            hipStreamSynchronize(c.s);
-        }
-    }
     if (st->decisions && st->decisions_cap > 0) {
         for (int i = 0; i < std::min((int)decisions.size(), st->decisions_cap); ++i) st->decisions[i] = decisions[i];
     }
@@ -571,87 +599,224 @@ void stats_fill(Ctx<T>& c, rpm_stats* st, const DevState& hs, int jvps, int grow
     }
 }
 
-// One solve (Algorithm 1 or 2) for the mean strain E.
+// What one run of the iteration solves: the cell problem for mean strain E
+// (err_mode 0), or a correction problem d = F(d; 0) + g (err_mode 1) whose
+// error is the fixed-point increment |G(d) - d| / |g|.
 template <typename T>
-rpm_status solve_impl(Ctx<T>& c, const rpm_problem* pr, const double E[6], const rpm_options* o, const T* eps0,
-                      T* eps_out, T* sig_out, double* sig_avg, rpm_stats* st, bool reuse)
+struct Spec {
+    const double* E;      // host mean strain
+    const T* eps0;        // device start (nullable)
+    bool zero_start;      // start from 0 (correction solves)
+    const T* shift;       // device shift field g (nullable)
+    int err_mode;
+    double tol;
+    double gnorm;
+    bool reuse;
+};
+
+template <typename T>
+struct SolveOut {
+    const T* final_it = nullptr;  // the iterate whose error was evaluated last
+    DevState hs;
+    int jvps = 0, growth = 0, p = 0;
+    std::vector<int> decisions;
+};
+
+// One run of Algorithm 1 or 2 (the iteration itself; outputs stay in the workspace).
+template <typename T>
+rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, const Spec<T>& sp, SolveOut<T>& so)
 {
-    auto t0 = std::chrono::steady_clock::now();
     const Geo& g = c.sh.g;
     const long long N = g.N;
     int p = 0;
-    rpm_status rs = prepare(c, pr, o, reuse, &p);
+    rpm_status rs = prepare(c, pr, o, sp.reuse, &p, sp.tol, sp.gnorm);
     if (rs != RPM_OK) return rs;
-    set_E(c, E);
+    set_E(c, sp.E);
     const bool rpm = o->scheme == RPM_SCHEME_RPM && c.pmax > 0;
     const int* done = &c.st->done;
+    double* pinc = sp.err_mode == 1 ? c.template at<double>(c.L.pinc) : nullptr;
     int jvps = 0, growth = 0;
-    std::vector<int> decisions;
 
-    // initial iterate eps^0 = E (or the supplied start) and xi^0 = F(eps^0)
-    if (eps0) {
-        hipMemcpyAsync(c.eps(), eps0, sizeof(T) * 6 * N, hipMemcpyDeviceToDevice, c.s);
+    // initial iterate eps^0 = E (or the supplied start, or 0) and xi^0 = F(eps^0)
+    if (sp.eps0) {
+        hipMemcpyAsync(c.eps(), sp.eps0, sizeof(T) * 6 * N, hipMemcpyDeviceToDevice, c.s);
     } else {
         const long long nel = 6 * N;
-        k_fill_uniform<T><<<(int)((nel + 255) / 256), 256, 0, c.s>>>(c.eps(), c.st->E, N);
+        k_fill_uniform<T><<<(int)((nel + 255) / 256), 256, 0, c.s>>>(c.eps(), sp.zero_start ? c.st->Ezero : c.st->E,
+                                                                     N);
     }
-    run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(1), OUT_XI, 0, DC_MEAN, c.st->E, done);
+    run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(1), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
     if (rpm) project(c, c.ring(1), c.eps(), p);
-    reduce_and_finalize(c, rpm ? p : 0, 1, 0, c.sh.Gp, done);
+    reduce_and_finalize(c, rpm ? p : 0, 1, 0, c.sh.Gp, done, sp.err_mode);
 
     int it = 1, nu = 0, nq = 0;
-    int hdone = 0;
     const int check = std::max(1, o->check_every);
     for (;;) {
         const bool at_growth = rpm && (nu > o->n_max) && p < c.pmax;
         if (at_growth || (it % check) == 0 || it >= o->max_iter) {
             int flags[4];
             if (!sync_read(c, flags, &c.st->done, sizeof(flags))) return RPM_E_HIP;
-            hdone = flags[0];
-            if (hdone || flags[2] >= o->max_iter) break;
+            if (flags[0] || flags[2] >= o->max_iter) break;
             if (at_growth) {
                 int want = 0;
-                const int added = grow_basis(c, it, nq, p, o, growth, &want, &jvps);
+                const int added = grow_basis(c, it, nq, p, o, (int)so.decisions.size(), &want, &jvps);
                 if (added < 0) return RPM_E_HIP;
-                decisions.push_back(want);
+                so.decisions.push_back(want);
                 ++growth;
                 nu = 0;
                 nq = 0;
                 // projections of the current pair (eps, xi) on the grown basis, Newton step
                 project(c, c.ring(it), c.eps(), p);
-                reduce_and_finalize(c, p, it, 1, c.sh.Gp, done);
+                reduce_and_finalize(c, p, it, 1, c.sh.Gp, done, sp.err_mode);
             }
         }
         // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step
         ++it;
         const T* xprev = c.ring(it - 1);
         if (rpm) {
-            run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done);
+            run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
             project(c, c.ring(it), c.eps(), p);
         } else {
-            run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done);
+            run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
         }
-        reduce_and_finalize(c, rpm ? p : 0, it, 0, c.sh.Gp, done);
+        reduce_and_finalize(c, rpm ? p : 0, it, 0, c.sh.Gp, done, sp.err_mode);
         ++nu;
         ++nq;
     }
-    DevState hs;
-    if (!sync_read(c, &hs, c.st, sizeof(hs))) return RPM_E_HIP;
-    // the iterate whose error was evaluated last
-    const int itf = std::max(hs.iters, 1);
-    const T* efin = (itf == 1 || rpm) ? c.eps() : c.ring(itf - 1);
-    if (eps_out) hipMemcpyAsync(eps_out, efin, sizeof(T) * 6 * N, hipMemcpyDeviceToDevice, c.s);
-    if (sig_out) {
-        k_stress<T><<<(int)((N + 255) / 256), 256, 0, c.s>>>(efin, c.phase, c.lame(), sig_out, N);
+    if (!sync_read(c, &so.hs, c.st, sizeof(DevState))) return RPM_E_HIP;
+    const int itf = std::max(so.hs.iters, 1);
+    so.final_it = (itf == 1 || rpm) ? c.eps() : c.ring(itf - 1);
+    so.jvps += jvps;
+    so.growth += growth;
+    so.p = p;
+    switch (so.hs.status) {
+        case 0: return RPM_OK;
+        case 2: return RPM_DIVERGED;
+        case 3: return RPM_SINGULAR;
+        default: return RPM_NOT_CONVERGED;
     }
+}
+
+// FP64 pipeline living in the FP32 workspace (certification and refinement).
+void sub64_init(Ctx<double>& c64, Ctx<float>& c, const rpm_options* o)
+{
+    const int32_t n[3] = {c.sh.g.nx, c.sh.g.ny, c.sh.g.nz};
+    const rpm_options b = basic_fp64_options(o);
+    c64.sh = make_shapes<double>(n);
+    c64.L = make_layout<double>(c64.sh, &b);
+    c64.s = c.s;
+    c64.ws = c.ws + c.L.sub64;
+    c64.st = reinterpret_cast<DevState*>(c64.ws + c64.L.st);
+    c64.phase = c.phase;
+    c64.lam0 = c.lam0;
+    c64.mu0 = c.mu0;
+    c64.pmax = 0;
+    c64.prof.on = false;
+}
+
+// FP64 map application on c64.eps(): xi64 in ring(1), error and sigma_hat(0) in hs.
+rpm_status eval64(Ctx<double>& c64, DevState& hs)
+{
+    k_reset_state<<<1, 1, 0, c64.s>>>(c64.st);
+    run_F<double>(c64, c64.eps(), 0, nullptr, c64.eps(), c64.ring(1), OUT_XI, 0, DC_MEAN, c64.st->E, nullptr);
+    reduce_and_finalize(c64, 0, 1, 0, c64.sh.Gp, nullptr);
+    if (!sync_read(c64, &hs, c64.st, sizeof(DevState))) return RPM_E_HIP;
+    return RPM_OK;
+}
+
+// Solve for E and write the caller's outputs; with FP32 fields, certify the
+// result in FP64 and refine it when the FP64 error misses tol.
+template <typename T>
+rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const rpm_options* o, const T* eps0,
+                      T* eps_out, T* sig_out, double* sig_avg, rpm_stats* st, bool reuse)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const long long N = c.sh.g.N;
+    const long long nel = 6 * N;
+    const int gb = (int)((nel + 255) / 256);
+    // FP32 fields carry ~1e-7 rounding, so equilibrium errors much below 1e-6 are
+    // not reliably reachable in FP32: with refinement on, the FP32 stage stops at
+    // max(tol, kFp32Stage) and FP64 refinement takes the field to tol.
+    const bool refine = sizeof(T) == 4 && o->refine > 0;
+    const double stage_tol = refine ? std::max(o->tol, kFp32Stage) : o->tol;
+    Spec<T> sp{E, eps0, false, nullptr, 0, stage_tol, 1.0, reuse};
+    SolveOut<T> so;
+    rpm_status rs = run_solve(c, pr, o, sp, so);
+    if (rs < 0) return rs;
+    const DevState hs_main = so.hs;
+    if (st && st->history && st->history_cap > 0) {  // before correction solves reuse the buffer
+        const int n = std::min(st->history_cap, hs_main.iters);
+        if (n > 0) {
+            hipMemcpyAsync(st->history, c.template at<double>(c.L.hist), sizeof(double) * n, hipMemcpyDeviceToHost,
+                           c.s);
+            hipStreamSynchronize(c.s);
+        }
+    }
+    double sav[6];
+    for (int i = 0; i < 6; ++i) sav[i] = so.hs.sig_hat0[i] / (double)N;
+    double res64 = so.hs.err;
+    int nref = 0;
+    const T* efin = so.final_it;
+    bool rounded = false;  // outputs come from the FP64 field rounded to T
+    if constexpr (sizeof(T) == 4) {
+        Ctx<double> c64;
+        sub64_init(c64, c, o);
+        int p64 = 0;
+        rs = prepare(c64, pr, o, false, &p64, o->tol);
+        if (rs != RPM_OK) return rs;
+        set_E(c64, E);
+        k_convert<T, double><<<gb, 256, 0, c.s>>>(efin, c64.eps(), 1.0, nel);
+        DevState h64;
+        if ((rs = eval64(c64, h64)) != RPM_OK) return rs;
+        res64 = h64.err;
+        for (int i = 0; i < 6; ++i) sav[i] = h64.sig_hat0[i] / (double)N;
+        const double zeros[6] = {0, 0, 0, 0, 0, 0};
+        T* g32 = c.template at<T>(c.L.shift);
+        while (rs == RPM_OK && so.hs.status == 0 && res64 > o->tol && nref < o->refine) {
+            // g = F64(eps64) - eps64, |g| in FP64
+            k_residual_shift<T><<<c.sh.Gp, kThreads, 0, c.s>>>(c64.ring(1), c64.eps(), g32, N, c.pg());
+            reduce_cols(c, c.pg(), c.sh.Gp, 1, 1, c.gsum());
+            double g2;
+            if (!sync_read(c, &g2, c.gsum(), sizeof(g2))) return RPM_E_HIP;
+            const double gnorm = std::sqrt(std::max(g2, 0.0));
+            if (!(gnorm > 0.0)) break;
+            Spec<T> sc{zeros, nullptr, true, g32, 1, o->refine_tol, gnorm, true};
+            SolveOut<T> si;
+            rpm_status ri = run_solve(c, pr, o, sc, si);
+            if (ri < 0) return ri;
+            so.jvps += si.jvps;
+            so.growth += si.growth;
+            so.p = si.p;
+            so.decisions.insert(so.decisions.end(), si.decisions.begin(), si.decisions.end());
+            k_add_correction<T><<<gb, 256, 0, c.s>>>(c64.eps(), si.final_it, nel);
+            if ((rs = eval64(c64, h64)) != RPM_OK) return rs;
+            res64 = h64.err;
+            for (int i = 0; i < 6; ++i) sav[i] = h64.sig_hat0[i] / (double)N;
+            ++nref;
+            if (ri != RPM_OK) break;
+        }
+        if (nref > 0) {
+            // the refined FP64 field, rounded, is the result
+            k_convert<double, T><<<gb, 256, 0, c.s>>>(c64.eps(), c.eps(), 1.0, nel);
+            efin = c.eps();
+            rounded = true;
+        }
+    }
+    if (eps_out) hipMemcpyAsync(eps_out, efin, sizeof(T) * nel, hipMemcpyDeviceToDevice, c.s);
+    if (sig_out) k_stress<T><<<(int)((N + 255) / 256), 256, 0, c.s>>>(efin, c.phase, c.lame(), sig_out, N);
     if (sig_avg)
-        for (int i = 0; i < 6; ++i) sig_avg[i] = hs.sig_hat0[i] / (double)N;
+        for (int i = 0; i < 6; ++i) sig_avg[i] = sav[i];
     if (hipStreamSynchronize(c.s) != hipSuccess || c.hip_error) return RPM_E_HIP;
     if (c.prof.on) c.prof.harvest();
+    (void)rounded;
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    stats_fill(c, st, hs, jvps, growth, p, secs, decisions);
-    switch (hs.status) {
-        case 0: return RPM_OK;
+    stats_fill(c, st, hs_main, so.jvps, so.growth, so.p, secs, so.decisions);
+    if (st) {
+        st->residual_fp64 = res64;
+        st->refinements = nref;
+    }
+    switch (hs_main.status) {
+        case 0: return (refine && !(res64 <= o->tol)) ? RPM_NOT_CONVERGED : RPM_OK;
         case 2: return RPM_DIVERGED;
         case 3: return RPM_SINGULAR;
         default: return RPM_NOT_CONVERGED;
@@ -682,6 +847,8 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->precision != RPM_FP64 && o->precision != RPM_FP32) return RPM_E_INVALID;
     if (o->check_every < 1) return RPM_E_INVALID;
     if (o->replay_len < 0 || (o->replay_len > 0 && !o->replay)) return RPM_E_INVALID;
+    if (o->refine < 0 || !finite(o->refine_tol) || !(o->refine_tol > 0.0) || !(o->refine_tol < 1.0))
+        return RPM_E_INVALID;
     return RPM_OK;
 }
 
@@ -720,7 +887,7 @@ rpm_status solve_typed(const rpm_problem* pr, const double E[6], const rpm_optio
     Ctx<T> c;
     rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
     if (rs != RPM_OK) return rs;
-    return solve_impl<T>(c, pr, E, o, (const T*)eps0, (T*)eps_out, (T*)sig_out, sig_avg, st, o->reuse_basis != 0);
+    return solve_full<T>(c, pr, E, o, (const T*)eps0, (T*)eps_out, (T*)sig_out, sig_avg, st, o->reuse_basis != 0);
 }
 
 template <typename T>
@@ -731,7 +898,7 @@ rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_optio
     rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
     if (rs != RPM_OK) return rs;
     int p = 0;
-    rs = prepare(c, pr, o, false, &p);
+    rs = prepare(c, pr, o, false, &p, o->tol);
     if (rs != RPM_OK) return rs;
     set_E(c, E);
     run_F<T>(c, (const T*)eps, 0, nullptr, (const T*)eps, (T*)xi, OUT_XI, 0, DC_MEAN, c.st->E, nullptr);
@@ -762,7 +929,7 @@ rpm_status eff_typed(const rpm_problem* pr, const rpm_options* o, double* C, rpm
         double sav[6];
         const bool reuse = o->reuse_basis != 0;
         c.prof.reset();
-        rs = solve_impl<T>(c, pr, E, o, nullptr, nullptr, nullptr, sav, st ? st + col : nullptr, reuse);
+        rs = solve_full<T>(c, pr, E, o, nullptr, nullptr, nullptr, sav, st ? st + col : nullptr, reuse);
         if (rs < 0) return rs;
         if (rs != RPM_OK && worst == RPM_OK) worst = rs;
         for (int row = 0; row < nc; ++row) {
@@ -793,6 +960,8 @@ void rpm_default_options(rpm_options* o)
     o->replay = nullptr;
     o->replay_len = 0;
     o->profile = 0;
+    o->refine = 4;
+    o->refine_tol = 1e-3;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
