@@ -79,7 +79,7 @@ enum { RPM_FP64 = 0,         /* fields, FFTs and Z in double                    
 
 /* kernel classes of rpm_stats.kernel_* (profile = 1) */
 enum { RPM_K_XFWD = 0, RPM_K_YFWD, RPM_K_GAMMA, RPM_K_YINV, RPM_K_XINV, RPM_K_REDUCE, RPM_K_FINAL,
-       RPM_K_GROWTH, RPM_K_PROJECT, RPM_NKERNEL };
+       RPM_K_GROWTH, RPM_K_PROJECT, RPM_K_RECOMBINE, RPM_NKERNEL };
 
 typedef struct {
     int32_t n[3];             /* nx, ny, nz                                      */

@@ -22,8 +22,8 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-RPM_NKERNEL = 9
-KERNEL_NAMES = ["xfwd", "yfwd", "gamma", "yinv", "xinv", "reduce", "finalize", "growth", "project"]
+RPM_NKERNEL = 10
+KERNEL_NAMES = ["xfwd", "yfwd", "gamma", "yinv", "xinv", "reduce", "finalize", "growth", "project", "recombine"]
 STATUS = {0: "RPM_OK", 1: "RPM_NOT_CONVERGED", 2: "RPM_DIVERGED", 3: "RPM_SINGULAR", -1: "RPM_E_INVALID",
           -2: "RPM_E_UNSUPPORTED_SIZE", -3: "RPM_E_WORKSPACE", -5: "RPM_E_HIP"}
 SCHEME = {"basic": 0, "rpm": 1}

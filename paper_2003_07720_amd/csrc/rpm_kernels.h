@@ -34,6 +34,16 @@ struct Geo {
     int two_d;
 };
 
+// Basis storage: Z (and W = F_u Z) in tiles of kZTile consecutive elements of
+// the 6N-vector; tile t holds its slice of all P column slots contiguously, so
+// element e of column j sits at zix(e, j, P).  Per-voxel recombination and the
+// lane-per-column projections then read long contiguous runs.
+constexpr int kZTile = 256;
+__host__ __device__ __forceinline__ long long zix(long long e, int j, int P)
+{
+    return ((e / kZTile) * (long long)P + j) * kZTile + (e % kZTile);
+}
+
 // Device-resident solver state (one per workspace).
 struct DevState {
     int magic;         // kStateMagic once the workspace has been initialised
@@ -89,7 +99,7 @@ struct MaxV<double> { static constexpr int v = 4; };
 // grid: nz * (ny / ty) blocks.  LDS: 2 * ty * (nx+1) + nx complex + reduction.
 // ---------------------------------------------------------------------------
 template <typename T, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const T* __restrict__ Z, int p,
+__global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const T* __restrict__ Z, int p, int zP,
                                                    const double* __restrict__ dco, T* __restrict__ eps_out,
                                                    const uint8_t* __restrict__ phase, const double* __restrict__ lame,
                                                    int use_ref, double lam0, double mu0, cx<T>* __restrict__ S1,
@@ -138,16 +148,16 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
             }
             for (int j = 0; j < p; ++j) {
                 const T dj = (T)dco[j];
-                const T* zj = Z + (long long)j * 6 * N + gi;
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
+                    const T* zj = Z + zix(c * N + gi, j, zP);
                     if constexpr (VEC) {
-                        const V t = *reinterpret_cast<const V*>(zj + c * N);
+                        const V t = *reinterpret_cast<const V*>(zj);
                         const T* ts = reinterpret_cast<const T*>(&t);
 #pragma unroll
                         for (int u = 0; u < VL; ++u) e[u][c] += dj * ts[u];
                     } else {
-                        e[0][c] += dj * zj[c * N];
+                        e[0][c] += dj * zj[0];
                     }
                 }
             }
@@ -551,7 +561,7 @@ constexpr int kCdBlock = 8 * kCdTile;
 
 template <typename TA, typename TZ, bool TWO>
 __global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, const TA* __restrict__ bv,
-                                                      const TZ* __restrict__ Z, int p, int pp, long long N,
+                                                      const TZ* __restrict__ Z, int p, int zP, int pp, long long N,
                                                       double* __restrict__ part, int ld)
 {
     constexpr int NV = TWO ? 2 : 1;
@@ -567,7 +577,6 @@ __global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, 
     const int sub = lane / pp;
     const int span = kCdTile / (kWaves * nsub);
     const int s0 = (wave * nsub + sub) * span;
-    const TZ* zc = Z + (long long)j * L6;
     double acc_a = 0.0, acc_b = 0.0, nrm = 0.0;
     const long long b0 = (long long)blockIdx.x * kCdBlock;
     for (int t = 0; t < kCdBlock / kCdTile; ++t) {
@@ -592,16 +601,16 @@ __global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, 
         if (j < p) {
             int n_here = ne - s0;
             n_here = n_here < 0 ? 0 : (n_here > span ? span : n_here);
-            const TZ* zp = zc + e0 + s0;
             const double* la = sa + s0;
             const double* lb = sb + (TWO ? s0 : 0);
             int k = 0;
-            if (((uintptr_t)zp & 15) == 0) {
+            // 32-element runs never straddle a tile (e0 + s0 is a multiple of 32)
+            if (((uintptr_t)Z & 15) == 0) {
                 using V = typename Vec4<TZ>::type;
                 constexpr int VW = sizeof(V) / sizeof(TZ);
                 for (; k + 32 <= n_here; k += 32) {
                     V zz[32 / VW];
-                    const V* zv = reinterpret_cast<const V*>(zp + k);
+                    const V* zv = reinterpret_cast<const V*>(Z + zix(e0 + s0 + k, j, zP));
 #pragma unroll
                     for (int u = 0; u < 32 / VW; ++u) zz[u] = zv[u];
                     const TZ* zs = reinterpret_cast<const TZ*>(zz);
@@ -613,7 +622,7 @@ __global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, 
                 }
             }
             for (; k < n_here; ++k) {
-                const double zz = (double)zp[k];
+                const double zz = (double)Z[zix(e0 + s0 + k, j, zP)];
                 acc_a += zz * la[k];
                 if (TWO) acc_b += zz * lb[k];
             }
@@ -648,7 +657,7 @@ __global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, 
 // v <- v - sum_j coef_j Z_j (coef device, p values); part[b] = <v, v> (Frobenius).
 template <typename TZ>
 __global__ __launch_bounds__(kThreads) void k_axpy_basis(double* __restrict__ v, const TZ* __restrict__ Z, int p,
-                                                         const double* __restrict__ coef, long long N,
+                                                         int zP, const double* __restrict__ coef, long long N,
                                                          double* __restrict__ part)
 {
     __shared__ double red[kWaves + 1];
@@ -662,7 +671,7 @@ __global__ __launch_bounds__(kThreads) void k_axpy_basis(double* __restrict__ v,
         const long long e = e0 + i;
         if (e >= L6) break;
         double t = v[e];
-        for (int j = 0; j < p; ++j) t -= cf[j] * (double)Z[(long long)j * L6 + e];
+        for (int j = 0; j < p; ++j) t -= cf[j] * (double)Z[zix(e, j, zP)];
         v[e] = t;
         acc[0] += (e < N3 ? 1.0 : 2.0) * t * t;
     }
@@ -894,6 +903,7 @@ constexpr int kChunk = kThreads * 8;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ xa, const T* __restrict__ xb,
                                                           const T* __restrict__ xc, const T* __restrict__ Z, int p,
+                                                          int zP,
                                                           const double* __restrict__ za,
                                                           const double* __restrict__ zb,
                                                           const double* __restrict__ zc, double* __restrict__ D1,
@@ -918,7 +928,7 @@ __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ 
             double d1 = (double)xa[o] - (double)xb[o];
             double d0 = xc ? ((double)xb[o] - (double)xc[o]) : 0.0;
             for (int j = 0; j < p; ++j) {
-                const double zz = (double)Z[(long long)j * 6 * N + o];
+                const double zz = (double)Z[zix(o, j, zP)];
                 d1 -= c1[j] * zz;
                 d0 -= c0[j] * zz;
             }
@@ -952,6 +962,58 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(double* __restrict__ y, 
         }
     }
     wg_sum_store<1>(acc, part + blockIdx.x, red);
+}
+
+// RPM recombination eps = xi + sum_j d_j Z_j as a streaming pass: each thread
+// handles runs of VL consecutive elements; for a column, a wave reads one
+// contiguous kilobyte of its tile.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi, const T* __restrict__ Z, int p,
+                                                        int zP, const double* __restrict__ dco,
+                                                        T* __restrict__ eps, long long n,
+                                                        const int* __restrict__ done)
+{
+    if (done && *done) return;
+    constexpr int VL = 16 / sizeof(T);
+    using V = typename Vec4<T>::type;
+    __shared__ T dj[kMaxP];
+    for (int j = threadIdx.x; j < p; j += kThreads) dj[j] = (T)dco[j];
+    __syncthreads();
+    const long long e = ((long long)blockIdx.x * kThreads + threadIdx.x) * VL;
+    if (e >= n) return;
+    if (e + VL <= n) {
+        V acc = *reinterpret_cast<const V*>(xi + e);
+        T* a = reinterpret_cast<T*>(&acc);
+#pragma unroll 4
+        for (int j = 0; j < p; ++j) {
+            const V z = *reinterpret_cast<const V*>(Z + zix(e, j, zP));
+            const T* zs = reinterpret_cast<const T*>(&z);
+#pragma unroll
+            for (int u = 0; u < VL; ++u) a[u] += dj[j] * zs[u];
+        }
+        *reinterpret_cast<V*>(eps + e) = acc;
+    } else {
+        for (long long i = e; i < n; ++i) {
+            T v = xi[i];
+            for (int j = 0; j < p; ++j) v += dj[j] * Z[zix(i, j, zP)];
+            eps[i] = v;
+        }
+    }
+}
+
+// Column j of a tiled basis <-> a contiguous 6N-vector (times scale on the way in).
+template <typename T>
+__global__ void k_col_get(const T* __restrict__ Z, int j, int zP, T* __restrict__ out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = Z[zix(i, j, zP)];
+}
+
+template <typename TI, typename T>
+__global__ void k_col_put(const TI* __restrict__ in, double scale, T* __restrict__ Z, int j, int zP, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) Z[zix(i, j, zP)] = (T)((double)in[i] * scale);
 }
 
 template <typename TI, typename TO>

@@ -27,6 +27,10 @@ constexpr size_t kAlign = 256;
 constexpr int kLdsCap = 60 * 1024;  // leaves room for static shared arrays
 constexpr int kMaxN = 512;
 constexpr double kFp32Stage = 1e-5;  // FP32 stage target before FP64 refinement
+#ifndef RPM_SPLIT_RECOMBINE
+#define RPM_SPLIT_RECOMBINE 1
+#endif
+constexpr bool kSplitRecombine = RPM_SPLIT_RECOMBINE != 0;  // recombination as its own pass
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -185,8 +189,10 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.tmp2 = take(pmax > 0 ? fT : 0);
     L.S1 = take(spec);
     L.S2 = take(g.two_d ? 0 : spec);
-    L.Z = take(fT * pmax);
-    L.W = take(fT * pmax);
+    // tiled basis: ceil(6N / kZTile) tiles of kZTile x p_max elements
+    const size_t zT = (size_t)((6 * g.N + kZTile - 1) / kZTile) * kZTile * sizeof(T);
+    L.Z = take(zT * pmax);
+    L.W = take(zT * pmax);
     L.D1 = take(pmax > 0 ? fD : 0);
     L.D0 = take(pmax > 0 ? fD : 0);
     // FP32 fields: shift field of the correction solves and an FP64 pipeline
@@ -283,8 +289,8 @@ struct Ctx {
     double* lame() { return at<double>(L.lame); }
     T* ring(int i) { return at<T>(L.ring[i & 3]); }
     T* eps() { return at<T>(L.eps); }
-    T* Zc(int j) { return at<T>(L.Z) + (size_t)j * 6 * sh.g.N; }
-    T* Wc(int j) { return at<T>(L.W) + (size_t)j * 6 * sh.g.N; }
+    T* Zb() { return at<T>(L.Z); }  // tiled basis Z (column slots: pmax)
+    T* Wb() { return at<T>(L.W); }  // tiled W = F_u Z
     double* sums() { return at<double>(L.sums); }
     double* gsum() { return at<double>(L.gsum); }
     double* pdots() { return at<double>(L.pdots); }
@@ -327,16 +333,28 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     // algorithmic bytes of each pass: inputs read once, outputs written once
     const double fieldB = 6.0 * (double)g.N * sizeof(T);
     const double specB = 6.0 * (double)g.nspec * sizeof(cx<T>);
-    const double bx = fieldB * (1 + p_corr + (eps_store ? 1 : 0)) + (use_ref ? 0.0 : (double)g.N) + specB;
     const double bi = specB + fieldB * (2 + (shift ? 1 : 0));
     hipEvent_t ev;
+    if (p_corr > 0 && kSplitRecombine) {
+        // eps = xin + Z d as its own streaming pass; the x pass then reads eps
+        const long long nel = 6 * g.N;
+        const int VL = 16 / (int)sizeof(T);
+        const int gb = (int)((nel / VL + kThreads - 1) / kThreads) + 1;
+        c.mark_begin(RPM_K_RECOMBINE, ev);
+        k_recombine<T><<<gb, kThreads, 0, c.s>>>(xin, c.Zb(), p_corr, c.pmax, c.st->d, eps_store, nel, done);
+        c.mark_end(RPM_K_RECOMBINE, ev, fieldB * (2 + p_corr));
+        xin = eps_store;
+        p_corr = 0;
+        eps_store = nullptr;
+    }
+    const double bx = fieldB * (1 + p_corr + (eps_store ? 1 : 0)) + (use_ref ? 0.0 : (double)g.N) + specB;
     c.mark_begin(RPM_K_XFWD, ev);
     if (g.nx % (16 / (int)sizeof(T)) == 0)
-        k_xfwd<T, true><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d,
+        k_xfwd<T, true><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zb() : nullptr, p_corr, c.pmax, c.st->d,
                                                             eps_store, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1,
                                                             pmean, g, sh.px, c.twx(), done);
     else
-        k_xfwd<T, false><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zc(0) : nullptr, p_corr, c.st->d,
+        k_xfwd<T, false><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zb() : nullptr, p_corr, c.pmax, c.st->d,
                                                              eps_store, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1,
                                                              pmean, g, sh.px, c.twx(), done);
     c.mark_end(RPM_K_XFWD, ev, bx);
@@ -370,10 +388,10 @@ int pow2_cols(int p)
 
 // Products <Z_j, a> (and <Z_j, b> or <a, a>) for j < p, per block of kCdBlock elements.
 template <typename TA, typename TZ, bool TWO>
-void launch_coldots(hipStream_t s, int G, const TA* a, const TA* b, const TZ* Z, int p, long long N, double* part,
-                    int ld)
+void launch_coldots(hipStream_t s, int G, const TA* a, const TA* b, const TZ* Z, int p, int zP, long long N,
+                    double* part, int ld)
 {
-    k_coldots<TA, TZ, TWO><<<G, kThreads, 0, s>>>(a, b, Z, p, pow2_cols(p), N, part, ld);
+    k_coldots<TA, TZ, TWO><<<G, kThreads, 0, s>>>(a, b, Z, p, zP, pow2_cols(p), N, part, ld);
 }
 
 // zeta_j = <Z_j, xi>, z_j = <Z_j, eps> partial sums for the Newton step.
@@ -383,7 +401,7 @@ void project(Ctx<T>& c, const T* xi, const T* eps, int p)
     if (p == 0) return;
     hipEvent_t ev;
     c.mark_begin(RPM_K_PROJECT, ev);
-    launch_coldots<T, T, true>(c.s, c.sh.Gp, xi, eps, c.Zc(0), p, c.sh.g.N, c.pdots(), c.L.ld);
+    launch_coldots<T, T, true>(c.s, c.sh.Gp, xi, eps, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
     c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * (2 + p));
 }
 
@@ -504,7 +522,8 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     const bool two = nq >= 3;
     hipEvent_t ev;
     c.mark_begin(RPM_K_GROWTH, ev);
-    k_growth_diff<T><<<Gg, kThreads, 0, c.s>>>(c.ring(sa), c.ring(sb), two ? c.ring(sc) : nullptr, c.Zc(0), p,
+    k_growth_diff<T><<<Gg, kThreads, 0, c.s>>>(c.ring(sa), c.ring(sb), two ? c.ring(sc) : nullptr, c.Zb(), p,
+                                               c.pmax,
                                                c.st->zeta_ring[sa], c.st->zeta_ring[sb], c.st->zeta_ring[sc], D1,
                                                two ? D0 : nullptr, N, c.pg());
     reduce_cols(c, c.pg(), Gg, 3, 3, c.gsum());
@@ -543,28 +562,31 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         double* coef = c.gsum();
         double* coef2 = c.sums() + kMaxP + 2;
         if (p > 0) {
-            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zc(0), p, N, c.pg(), p + 1);
+            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), p + 1);
             reduce_cols(c, c.pg(), Gp, p + 1, p, coef);
-            k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zc(0), p, coef, N, c.pg());
-            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zc(0), p, N, c.pg(), p + 1);
+            k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zb(), p, c.pmax, coef, N, c.pg());
+            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), p + 1);
             reduce_cols(c, c.pg(), Gp, p + 1, p, coef2);
         }
-        k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zc(0), p, coef2, N, c.pg());
+        k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zb(), p, c.pmax, coef2, N, c.pg());
         reduce_cols(c, c.pg(), Gp, 1, 1, coef + kMaxP);
         double n2;
         if (!sync_read(c, &n2, coef + kMaxP, sizeof(n2))) return -1;
         const double vn = std::sqrt(std::max(n2, 0.0));
         if (!(vn > 1e-10)) continue;
-        k_convert<double, T><<<gb, 256, 0, c.s>>>(v, c.Zc(p), 1.0 / vn, nel);
+        // store z_p in the basis and keep a contiguous copy (tmp) for the map
+        k_col_put<double, T><<<gb, 256, 0, c.s>>>(v, 1.0 / vn, c.Zb(), p, c.pmax, nel);
+        k_col_get<T><<<gb, 256, 0, c.s>>>(c.Zb(), p, c.pmax, tmp, nel);
         // Jacobian-vector product w = F(z_p; E = 0): new column <z_i, w> (i <= p) of H
-        run_F<T>(c, c.Zc(p), 0, nullptr, c.Zc(p), c.Wc(p), OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
+        run_F<T>(c, tmp, 0, nullptr, tmp, tmp2, OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
+        k_col_put<T, T><<<gb, 256, 0, c.s>>>(tmp2, 1.0, c.Wb(), p, c.pmax, nel);
         double* hcol = c.sums() + 1;
-        launch_coldots<T, T, false>(c.s, Gp, c.Wc(p), nullptr, c.Zc(0), p + 1, N, c.pg(), p + 2);
+        launch_coldots<T, T, false>(c.s, Gp, tmp2, nullptr, c.Zb(), p + 1, c.pmax, N, c.pg(), p + 2);
         reduce_cols(c, c.pg(), Gp, p + 2, p + 1, hcol);
         // new row: <z_p, w_j> for j < p
         double* row = c.gsum();
         if (p > 0) {
-            launch_coldots<T, T, false>(c.s, Gp, c.Zc(p), nullptr, c.Wc(0), p, N, c.pg(), p + 1);
+            launch_coldots<T, T, false>(c.s, Gp, tmp, nullptr, c.Wb(), p, c.pmax, N, c.pg(), p + 1);
             reduce_cols(c, c.pg(), Gp, p + 1, p, row);
         }
         k_border<<<1, 1, 0, c.s>>>(c.st, hcol, row, p);
