@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle map applications in the CPU sample")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="after the run, copy a float32 buffer of this many MiB three times (a plain copy kernel "
+                         "of known size that scales hardware byte counters)")
     return ap.parse_args()
 
 
@@ -170,6 +173,12 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if a.calibrate_copy_mib > 0:
+        x = torch.ones(a.calibrate_copy_mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

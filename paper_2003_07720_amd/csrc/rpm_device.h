@@ -1,5 +1,5 @@
 // Device building blocks of the gfx950 RPM-FFT path: complex arithmetic,
-// radix-2/3/4/8 butterflies, an LDS-resident Stockham FFT stage shared by all
+// radix-2/3/4/8/16 butterflies, an LDS-resident Stockham FFT stage shared by all
 // pencil passes, and deterministic workgroup reductions.
 #pragma once
 
@@ -101,13 +101,58 @@ __device__ __forceinline__ void dft8(cx<T>* v)
     v[7] = csub(e[3], o3);
 }
 
+// Length 16 as 4 x 4: DFT-4 over the stride-4 subsequences, twiddles
+// w16^(n2 k1), DFT-4 across them; output index k1 + 4 k2.
+template <typename T, int D>
+__device__ __forceinline__ void dft16(cx<T>* v)
+{
+    // cos and sin of 2 pi m / 16, m = 0..3
+    const T c1 = T(0.92387953251128675612818318939679), s1 = T(0.38268343236508977172845998403040);
+    const T r2 = T(0.70710678118654752440084436210485);
+    cx<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        cx<T> t[4] = {v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]};
+        dft4<T, D>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+    }
+    // twiddles exp(D 2 pi i m / 16) for m = n2 * k1
+    auto tw = [&](cx<T> a, int m) -> cx<T> {
+        T c, s;
+        switch (m) {
+            case 1: c = c1; s = s1; break;
+            case 2: c = r2; s = r2; break;
+            case 3: c = s1; s = c1; break;
+            case 4: c = T(0); s = T(1); break;
+            case 6: c = -r2; s = r2; break;
+            case 9: c = -c1; s = -s1; break;
+            default: c = T(1); s = T(0); break;
+        }
+        s = D * s;
+        return cx<T>{a.x * c - a.y * s, a.x * s + a.y * c};
+    };
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) y[n2][k1] = tw(y[n2][k1], n2 * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cx<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        dft4<T, D>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+}
+
 template <typename T, int R, int D>
 __device__ __forceinline__ void dftR(cx<T>* v)
 {
     if constexpr (R == 2) dft2<T, D>(v);
     else if constexpr (R == 3) dft3<T, D>(v);
     else if constexpr (R == 4) dft4<T, D>(v);
-    else dft8<T, D>(v);
+    else if constexpr (R == 8) dft8<T, D>(v);
+    else dft16<T, D>(v);
 }
 
 // One Stockham stage over nseq sequences of length n held in LDS with row
@@ -155,7 +200,8 @@ __device__ cx<T>* lds_fft(cx<T>* a, cx<T>* b, const Plan& pl, int nseq, int ss, 
     cx<T>* dst = b;
     for (int st = 0; st < pl.nst; ++st) {
         const int R = pl.rad[st];
-        if (R == 8) fft_stage<T, 8, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        if (R == 16) fft_stage<T, 16, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else if (R == 8) fft_stage<T, 8, D>(src, dst, pl.n, Ns, nseq, ss, tw);
         else if (R == 4) fft_stage<T, 4, D>(src, dst, pl.n, Ns, nseq, ss, tw);
         else if (R == 2) fft_stage<T, 2, D>(src, dst, pl.n, Ns, nseq, ss, tw);
         else fft_stage<T, 3, D>(src, dst, pl.n, Ns, nseq, ss, tw);

@@ -273,6 +273,88 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(const cx<T>* __restrict__ S1,
     }
 }
 
+// Software-pipelined y passes: a persistent grid walks the tiles; each thread
+// keeps its share of the next tile in registers (loads in flight during the
+// current tile's LDS transform and stores).  PT bounds tz * ny / kThreads.
+template <typename T, int D, int PT>
+__global__ __launch_bounds__(kThreads) void k_ypipe(const cx<T>* __restrict__ Sin, cx<T>* __restrict__ Sout, Geo g,
+                                                    Plan py, const cx<T>* __restrict__ twy, int ntiles,
+                                                    const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int ny = g.ny, tz = g.tz, ss = ny + 1;
+    cx<T>* A = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B = A + tz * ss;
+    cx<T>* tw = B + tz * ss;
+    const int nzt = g.nz / tz;
+    const int nel = tz * ny;
+    for (int i = threadIdx.x; i < ny; i += kThreads) tw[i] = twy[i];
+    cx<T> pre[PT];
+    // forward (D < 0): tile rows are contiguous in S1; inverse: TZ-segments of S2
+    auto load = [&](int t) {
+        int b = t;
+        const int zt = b % nzt;
+        b /= nzt;
+        const int kx = b % g.nh;
+        const int c = b / g.nh;
+        const int z0 = zt * tz;
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < nel) {
+                if (D < 0) {
+                    pre[u] = Sin[(long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny + e];
+                } else {
+                    const int r = e % tz, ky = e / tz;
+                    pre[u] = Sin[(long long)c * g.nspec + ((long long)ky * g.nh + kx) * g.nz + z0 + r];
+                }
+            }
+        }
+    };
+    int t = blockIdx.x;
+    if (t < ntiles) load(t);
+    for (; t < ntiles; t += gridDim.x) {
+        __syncthreads();  // the previous tile's stores have read A/B
+#pragma unroll
+        for (int u = 0; u < PT; ++u) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < nel) {
+                if (D < 0) {
+                    const int r = e / ny, y = e - (e / ny) * ny;
+                    A[r * ss + y] = pre[u];
+                } else {
+                    const int r = e % tz, ky = e / tz;
+                    A[r * ss + ky] = pre[u];
+                }
+            }
+        }
+        __syncthreads();
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(tn);  // next tile in flight during the transform
+        const cx<T>* R = lds_fft<T, D>(A, B, py, tz, ss, tw);
+        int b = t;
+        const int zt = b % nzt;
+        b /= nzt;
+        const int kx = b % g.nh;
+        const int c = b / g.nh;
+        const int z0 = zt * tz;
+        if (D < 0) {
+            cx<T>* dst = Sout + (long long)c * g.nspec;
+            for (int e = threadIdx.x; e < nel; e += kThreads) {
+                const int r = e % tz, ky = e / tz;
+                dst[((long long)ky * g.nh + kx) * g.nz + z0 + r] = R[r * ss + ky];
+            }
+        } else {
+            cx<T>* dst = Sout + (long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny;
+            for (int e = threadIdx.x; e < nel; e += kThreads) {
+                const int r = e / ny, y = e - r * ny;
+                dst[e] = R[r * ss + y];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // y-inverse: S2[c][ky][kx][z] -> inverse FFT along y -> S1[c][kx][z][y].
 // ---------------------------------------------------------------------------

@@ -31,6 +31,14 @@ constexpr double kFp32Stage = 1e-5;  // FP32 stage target before FP64 refinement
 #define RPM_SPLIT_RECOMBINE 1
 #endif
 constexpr bool kSplitRecombine = RPM_SPLIT_RECOMBINE != 0;  // recombination as its own pass
+#ifndef RPM_YPIPE
+#define RPM_YPIPE 1
+#endif
+#ifndef RPM_YPIPE_BLOCKS
+#define RPM_YPIPE_BLOCKS 1024
+#endif
+constexpr bool kYPipe = RPM_YPIPE != 0;        // software-pipelined y passes
+constexpr int kYPipeBlocks = RPM_YPIPE_BLOCKS;  // persistent grid of the pipelined y passes
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -55,6 +63,10 @@ Plan make_plan(int n)
     while (m % 3 == 0) {
         m /= 3;
         ++threes;
+    }
+    while (twos >= 4) {
+        p.rad[p.nst++] = 16;
+        twos -= 4;
     }
     while (twos >= 3) {
         p.rad[p.nst++] = 8;
@@ -360,7 +372,11 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     c.mark_end(RPM_K_XFWD, ev, bx);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YFWD, ev);
-        k_yfwd<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
+        if (kYPipe && g.tz * g.ny <= 8 * kThreads)
+            k_ypipe<T, -1, 8><<<std::min(sh.Gy, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
+                                                                                           c.twy(), sh.Gy, done);
+        else
+            k_yfwd<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
         c.mark_end(RPM_K_YFWD, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_GAMMA, ev);
@@ -369,7 +385,11 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     c.mark_end(RPM_K_GAMMA, ev, 2.0 * specB);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
-        k_yinv<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py, c.twy(), done);
+        if (kYPipe && g.tz * g.ny <= 8 * kThreads)
+            k_ypipe<T, 1, 8><<<std::min(sh.Gy, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
+                                                                                          c.twy(), sh.Gy, done);
+        else
+            k_yinv<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py, c.twy(), done);
         c.mark_end(RPM_K_YINV, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_XINV, ev);
