@@ -67,6 +67,8 @@ struct DevState {
     double zeta_ring[4][kMaxP];
     double H[kMaxP * kMaxP];
     double LU[kMaxP * kMaxP];
+    double G[kMaxP * kMaxP];     // Gram matrix <Z_i, Z_j> of the stored columns
+    double AinvT[kMaxP * kMaxP]; // (I - H)^{-1}, transposed: AinvT[j * kMaxP + i] = inv[i][j]
     int piv[kMaxP];
 };
 
@@ -627,143 +629,303 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
 }
 
 // ---------------------------------------------------------------------------
-// Products with the basis Z (column-major, column j at Z + j * 6N).
-// One lane per column: lane l works on column j = l mod pp (pp = power of two
-// >= p, <= 64) over its own stretch of elements, streaming its column with
-// 16-byte loads; the field values, shared by all columns, are staged once per
-// tile in LDS (weighted by the Frobenius weight) and read as broadcasts.
-//   part[b][j]      = sum_e w(e) Z_j[e] a[e]          (j < p)
-//   part[b][ld + j] = sum_e w(e) Z_j[e] bv[e]         (TWO)
-//   part[b][p]      = sum_e w(e) a[e]^2               (!TWO)
+// Products with the tiled basis Z.  A wave owns whole tiles of kZTile
+// elements; lane l holds elements 4l .. 4l+3 of its tile, so the slice of
+// column j in that tile is one coalesced read (1 KB for float), and the lane
+// keeps one FP64 accumulator per column and field:
+//   part[b * rs + f * ld + j] = sum_e w(e) Z_j[e] a_f[e]      (j < p, f < NF)
 // w(e) = 1 on the normal components (e < 3N), 2 on the shear ones.
-// Each block covers kCdBlock consecutive elements of the 6N-vector.
+// UPD: a_0 <- a_0 - sum_j coef_j Z_j first (written back; the products are
+//      then those of the updated field).
+// NRM: part[b * rs + NF * ld] = sum_e w(e) a_0[e]^2 (after the update).
+// PC is a compile-time bound on p (accumulators live in registers).  Block b
+// takes tiles b * kWaves + wave + k * gridDim.x * kWaves: a fixed assignment,
+// so the sums are reproducible.
 // ---------------------------------------------------------------------------
-constexpr int kCdTile = 2048;
-constexpr int kCdBlock = 8 * kCdTile;
+// Four consecutive elements as raw 16- or 32-byte loads, converted on use.
+template <typename T>
+struct Raw4;
+template <>
+struct Raw4<float> {
+    float4 v;
+    __device__ __forceinline__ void load(const float* __restrict__ p) { v = *reinterpret_cast<const float4*>(p); }
+    __device__ __forceinline__ void load_tail(const float* __restrict__ p, long long e0, long long L6)
+    {
+        v.x = e0 < L6 ? p[0] : 0.f;
+        v.y = e0 + 1 < L6 ? p[1] : 0.f;
+        v.z = e0 + 2 < L6 ? p[2] : 0.f;
+        v.w = e0 + 3 < L6 ? p[3] : 0.f;
+    }
+    __device__ __forceinline__ void get(double (&o)[4]) const
+    {
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+template <>
+struct Raw4<double> {
+    double2 a, b;
+    __device__ __forceinline__ void load(const double* __restrict__ p)
+    {
+        a = *reinterpret_cast<const double2*>(p);
+        b = *reinterpret_cast<const double2*>(p + 2);
+    }
+    __device__ __forceinline__ void load_tail(const double* __restrict__ p, long long e0, long long L6)
+    {
+        a.x = e0 < L6 ? p[0] : 0.0;
+        a.y = e0 + 1 < L6 ? p[1] : 0.0;
+        b.x = e0 + 2 < L6 ? p[2] : 0.0;
+        b.y = e0 + 3 < L6 ? p[3] : 0.0;
+    }
+    __device__ __forceinline__ void get(double (&o)[4]) const
+    {
+        o[0] = a.x;
+        o[1] = a.y;
+        o[2] = b.x;
+        o[3] = b.y;
+    }
+};
 
-template <typename TA, typename TZ, bool TWO>
-__global__ __launch_bounds__(kThreads) void k_coldots(const TA* __restrict__ a, const TA* __restrict__ bv,
-                                                      const TZ* __restrict__ Z, int p, int zP, int pp, long long N,
-                                                      double* __restrict__ part, int ld)
+// Column-group products (no update): wave g of a block of 64 * ceil(p / 8)
+// threads owns columns 8g .. 8g+7 and streams their slices of every tile the
+// block visits (tiles b, b + G, ...), so a wave keeps only 8 accumulators per
+// field and issues its 8 column loads together; the waves of a block read the
+// same field slice (one HBM read, the rest from cache).  Slices are addressed
+// as a wave-uniform base plus the lane offset.  Partial sums are
+// column-major: part[(f * ld + j) * G + b], G = gridDim.x.
+template <bool FULL, typename TA, typename TZ, int NF>
+__device__ __forceinline__ void gdots_tile(const TA* __restrict__ a0t, const TA* __restrict__ a1t,
+                                           const TZ* __restrict__ zt, int lo, int nj, long long e0, long long L6,
+                                           long long N3, double (&acc)[NF][8])
 {
-    constexpr int NV = TWO ? 2 : 1;
-    __shared__ double sa[kCdTile];
-    __shared__ double sb[TWO ? kCdTile : 1];
-    __shared__ double red[kWaves * 64 * NV];
-    __shared__ double nred[kWaves];
-    const long long L6 = 6 * N;
-    const long long N3 = 3 * N;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int j = lane & (pp - 1);
-    const int nsub = 64 / pp;
-    const int sub = lane / pp;
-    const int span = kCdTile / (kWaves * nsub);
-    const int s0 = (wave * nsub + sub) * span;
-    double acc_a = 0.0, acc_b = 0.0, nrm = 0.0;
-    const long long b0 = (long long)blockIdx.x * kCdBlock;
-    for (int t = 0; t < kCdBlock / kCdTile; ++t) {
-        const long long e0 = b0 + (long long)t * kCdTile;
-        if (e0 >= L6) break;
-        const int ne = (int)((L6 - e0) < kCdTile ? (L6 - e0) : kCdTile);
-        __syncthreads();
-        for (int i = threadIdx.x; i < kCdTile; i += kThreads) {
-            double va = 0.0, vb = 0.0;
-            if (i < ne) {
-                const long long e = e0 + i;
-                const double w = e < N3 ? 1.0 : 2.0;
-                va = (double)a[e];
-                if (!TWO) nrm += w * va * va;
-                va *= w;
-                if (TWO) vb = w * (double)bv[e];
-            }
-            sa[i] = va;
-            if (TWO) sb[i] = vb;
-        }
-        __syncthreads();
-        if (j < p) {
-            int n_here = ne - s0;
-            n_here = n_here < 0 ? 0 : (n_here > span ? span : n_here);
-            const double* la = sa + s0;
-            const double* lb = sb + (TWO ? s0 : 0);
-            int k = 0;
-            // 32-element runs never straddle a tile (e0 + s0 is a multiple of 32)
-            if (((uintptr_t)Z & 15) == 0) {
-                using V = typename Vec4<TZ>::type;
-                constexpr int VW = sizeof(V) / sizeof(TZ);
-                for (; k + 32 <= n_here; k += 32) {
-                    V zz[32 / VW];
-                    const V* zv = reinterpret_cast<const V*>(Z + zix(e0 + s0 + k, j, zP));
+    double w[4], f0[4], f1[4];
 #pragma unroll
-                    for (int u = 0; u < 32 / VW; ++u) zz[u] = zv[u];
-                    const TZ* zs = reinterpret_cast<const TZ*>(zz);
+    for (int u = 0; u < 4; ++u) w[u] = (FULL || e0 + u < L6) ? (e0 + u < N3 ? 1.0 : 2.0) : 0.0;
+    Raw4<TA> r0, r1;
+    Raw4<TZ> raw[8];
+    if (FULL) {
+        r0.load(a0t + lo);
+        if (NF > 1) r1.load(a1t + lo);
+    } else {
+        r0.load_tail(a0t + lo, e0, L6);
+        if (NF > 1) r1.load_tail(a1t + lo, e0, L6);
+    }
+    // slots past the group's last column repeat it (valid memory); their sums
+    // are never stored
 #pragma unroll
-                    for (int u = 0; u < 32; ++u) {
-                        acc_a += (double)zs[u] * la[k + u];
-                        if (TWO) acc_b += (double)zs[u] * lb[k + u];
-                    }
-                }
-            }
-            for (; k < n_here; ++k) {
-                const double zz = (double)Z[zix(e0 + s0 + k, j, zP)];
-                acc_a += zz * la[k];
-                if (TWO) acc_b += zz * lb[k];
-            }
+    for (int u = 0; u < 8; ++u) {
+        const TZ* zc = zt + (long long)min(u, nj - 1) * kZTile;
+        if (FULL) raw[u].load(zc + lo);
+        else raw[u].load_tail(zc + lo, e0, L6);
+    }
+    r0.get(f0);
+    if (NF > 1) r1.get(f1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f0[q] *= w[q];
+        if (NF > 1) f1[q] *= w[q];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        double z[4];
+        raw[u].get(z);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc[0][u] += z[q] * f0[q];
+            if (NF > 1) acc[NF - 1][u] += z[q] * f1[q];
         }
-    }
-    red[(wave * 64 + lane) * NV] = acc_a;
-    if (TWO) red[(wave * 64 + lane) * NV + 1] = acc_b;
-    if (!TWO) {
-        const double s = wave_sum(nrm);
-        if (lane == 0) nred[wave] = s;
-    }
-    __syncthreads();
-    const long long rowst = TWO ? 2LL * ld : (long long)ld;
-    if ((int)threadIdx.x < p) {
-        double ta = 0.0, tb = 0.0;
-        for (int w = 0; w < kWaves; ++w)
-            for (int q = 0; q < nsub; ++q) {
-                const int idx = (w * 64 + q * pp + threadIdx.x) * NV;
-                ta += red[idx];
-                if (TWO) tb += red[idx + 1];
-            }
-        part[(long long)blockIdx.x * rowst + threadIdx.x] = ta;
-        if (TWO) part[(long long)blockIdx.x * rowst + ld + threadIdx.x] = tb;
-    }
-    if (!TWO && threadIdx.x == 0) {
-        double tn = 0.0;
-        for (int w = 0; w < kWaves; ++w) tn += nred[w];
-        part[(long long)blockIdx.x * rowst + p] = tn;
     }
 }
 
-// v <- v - sum_j coef_j Z_j (coef device, p values); part[b] = <v, v> (Frobenius).
-template <typename TZ>
-__global__ __launch_bounds__(kThreads) void k_axpy_basis(double* __restrict__ v, const TZ* __restrict__ Z, int p,
-                                                         int zP, const double* __restrict__ coef, long long N,
-                                                         double* __restrict__ part)
+template <typename TA, typename TZ, int NF>
+__global__ __launch_bounds__(512) void k_gdots(const TA* __restrict__ a0, const TA* __restrict__ a1,
+                                               const TZ* __restrict__ Z, int p, int zP, long long N,
+                                               double* __restrict__ part, int ld)
 {
-    __shared__ double red[kWaves + 1];
-    __shared__ double cf[kMaxP];
-    for (int j = threadIdx.x; j < p; j += kThreads) cf[j] = coef[j];
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int j0 = 8 * g;
+    const int nj = min(8, p - j0);  // >= 1: the block has ceil(p / 8) waves
+    const int lo = 4 * lane;
     const long long L6 = 6 * N, N3 = 3 * N;
-    double acc[1] = {0.0};
-    const long long e0 = (long long)blockIdx.x * kCdBlock;
-    for (int i = threadIdx.x; i < kCdBlock; i += kThreads) {
-        const long long e = e0 + i;
-        if (e >= L6) break;
-        double t = v[e];
-        for (int j = 0; j < p; ++j) t -= cf[j] * (double)Z[zix(e, j, zP)];
-        v[e] = t;
-        acc[0] += (e < N3 ? 1.0 : 2.0) * t * t;
+    const long long nfull = L6 / kZTile;
+    double acc[NF][8];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[f][u] = 0.0;
+    long long tile = blockIdx.x;
+    for (; tile < nfull; tile += gridDim.x)
+        gdots_tile<true, TA, TZ, NF>(a0 + tile * kZTile, a1 + tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile,
+                                     lo, nj, tile * kZTile + lo, L6, N3, acc);
+    if (tile == nfull && nfull * kZTile < L6)  // the last, partial tile
+        gdots_tile<false, TA, TZ, NF>(a0 + tile * kZTile, a1 + tile * kZTile,
+                                      Z + (tile * zP + j0) * (long long)kZTile, lo, nj, tile * kZTile + lo, L6, N3,
+                                      acc);
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double sum = wave_sum(acc[f][u]);
+            if (lane == 0 && u < nj) part[(long long)(f * ld + j0 + u) * gridDim.x + blockIdx.x] = sum;
+        }
+}
+
+// One tile of k_tdots for one lane: elements e0 .. e0+3 (FULL: all inside the
+// vector, no guards).
+template <bool FULL, typename TA, typename TZ, int NF, int PC, bool UPD, bool NRM>
+__device__ __forceinline__ void tdots_tile(TA* __restrict__ a0, const TA* __restrict__ a1,
+                                           const TZ* __restrict__ zt, long long e0, long long L6, long long N3,
+                                           int p, const double* cf, double (&acc)[NF][PC], double& nrm)
+{
+    constexpr int CG = 8;  // columns whose loads are issued together
+    double w[4], f0[4], f1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = (FULL || e0 + u < L6) ? (e0 + u < N3 ? 1.0 : 2.0) : 0.0;
+    if (FULL) {
+        Raw4<TA> r0;
+        r0.load(a0 + e0);
+        r0.get(f0);
+        if (NF > 1) {
+            Raw4<TA> r1;
+            r1.load(a1 + e0);
+            r1.get(f1);
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            f0[u] = e0 + u < L6 ? (double)a0[e0 + u] : 0.0;
+            f1[u] = (NF > 1 && e0 + u < L6) ? (double)a1[e0 + u] : 0.0;
+        }
     }
-    wg_sum_store<1>(acc, part + blockIdx.x, red);
+    // columns past p in a load group are clamped to column p - 1 (valid memory)
+    // and carry weight zero; values stay in their storage type until used
+    auto load_group = [&](int g, Raw4<TZ> (&raw)[CG]) {
+#pragma unroll
+        for (int u = 0; u < CG; ++u) {
+            const TZ* zc = zt + (long long)min(g * CG + u, p - 1) * kZTile;
+            if (FULL) raw[u].load(zc);
+            else raw[u].load_tail(zc, e0, L6);
+        }
+    };
+    if (UPD) {
+#pragma unroll
+        for (int g = 0; g < PC / CG; ++g) {
+            if (g * CG < p) {
+                Raw4<TZ> raw[CG];
+                load_group(g, raw);
+#pragma unroll
+                for (int u = 0; u < CG; ++u) {
+                    const double c = cf[g * CG + u];  // zero past p
+                    double z[4];
+                    raw[u].get(z);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) f0[q] -= c * z[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (FULL || e0 + q < L6) a0[e0 + q] = (TA)f0[q];
+    }
+    if (NRM) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nrm += w[q] * f0[q] * f0[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f0[q] *= w[q];
+        if (NF > 1) f1[q] *= w[q];
+    }
+#pragma unroll
+    for (int g = 0; g < PC / CG; ++g) {
+        if (g * CG < p) {
+            Raw4<TZ> raw[CG];
+            load_group(g, raw);
+#pragma unroll
+            for (int u = 0; u < CG; ++u) {
+                const double m = g * CG + u < p ? 1.0 : 0.0;
+                double z[4];
+                raw[u].get(z);
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    s0 += z[q] * f0[q];
+                    if (NF > 1) s1 += z[q] * f1[q];
+                }
+                acc[0][g * CG + u] += m * s0;
+                if (NF > 1) acc[NF - 1][g * CG + u] += m * s1;
+            }
+        }
+    }
+}
+
+template <typename TA, typename TZ, int NF, int PC, bool UPD, bool NRM>
+__global__ __launch_bounds__(kThreads) void k_tdots(TA* __restrict__ a0, const TA* __restrict__ a1,
+                                                    const TZ* __restrict__ Z, int p, int zP,
+                                                    const double* __restrict__ coef, long long N,
+                                                    double* __restrict__ part, int ld, int rs)
+{
+    constexpr int NA = NF * PC + (NRM ? 1 : 0);
+    static_assert(PC % 8 == 0, "column capacity is a multiple of the load group");
+    __shared__ double red[kWaves][NA];
+    __shared__ double cf[UPD ? PC : 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (UPD) {
+        for (int j = threadIdx.x; j < PC; j += kThreads) cf[j] = j < p ? coef[j] : 0.0;
+        __syncthreads();
+    }
+    const long long L6 = 6 * N, N3 = 3 * N;
+    const long long nfull = L6 / kZTile;
+    double acc[NF][PC];
+    double nrm = 0.0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int j = 0; j < PC; ++j) acc[f][j] = 0.0;
+    const long long stride = (long long)gridDim.x * kWaves;
+    const long long first = (long long)blockIdx.x * kWaves + wave;
+    long long tile = first;
+    for (; tile < nfull; tile += stride)
+        tdots_tile<true, TA, TZ, NF, PC, UPD, NRM>(a0, a1, Z + tile * (long long)zP * kZTile + 4 * lane,
+                                                   tile * kZTile + 4 * lane, L6, N3, p, cf, acc, nrm);
+    if (tile == nfull && nfull * kZTile < L6)  // the last, partial tile
+        tdots_tile<false, TA, TZ, NF, PC, UPD, NRM>(a0, a1, Z + tile * (long long)zP * kZTile + 4 * lane,
+                                                    tile * kZTile + 4 * lane, L6, N3, p, cf, acc, nrm);
+    // fixed-order reductions: across the wave, then across the waves
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int j = 0; j < PC; ++j) {
+            if (j < p) {
+                const double s = wave_sum(acc[f][j]);
+                if (lane == 0) red[wave][f * PC + j] = s;
+            }
+        }
+    if (NRM) {
+        const double s = wave_sum(nrm);
+        if (lane == 0) red[wave][NF * PC] = s;
+    }
+    __syncthreads();
+    double* out = part + (long long)blockIdx.x * rs;
+    for (int i = threadIdx.x; i < NA; i += kThreads) {
+        const int f = i / PC, j = i - f * PC;
+        if (f < NF && j >= p) continue;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) s += red[q][i];
+        out[f < NF ? f * ld + j : NF * ld] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Reductions of per-block partial sums (fixed order: deterministic).
-// out[0] = sum of part_err; out[1 + o] for o < 2p = column map(o) of
-// part_dots (zeta_j at column j, z_j at column ld + j).  grid: 1 + 2p.
+// out[0] = sum of part_err; out[1 + o] for o < nf * p = column map(o) of
+// part_dots (zeta_j at column j, z_j at column ld + j; column-major, G_dots
+// partials per column).
+// grid: 1 + nf * p.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_reduce_main(const double* __restrict__ part_err, int G_err,
                                                           const double* __restrict__ part_dots, int G_dots, int ld,
@@ -781,22 +943,22 @@ __global__ __launch_bounds__(kThreads) void k_reduce_main(const double* __restri
     } else {
         const int q = o - 1;
         const int col = q < p ? q : ld + (q - p);
-        for (int b = threadIdx.x; b < G_dots; b += kThreads) acc += part_dots[(long long)b * 2 * ld + col];
+        for (int b = threadIdx.x; b < G_dots; b += kThreads) acc += part_dots[(long long)col * G_dots + b];
     }
     double v[1] = {acc};
     wg_sum_store<1>(v, tot, red);
     if (threadIdx.x == 0) out[o] = tot[0];
 }
 
-// out[j] = sum_b part[b * ld + j], j < m.  grid: m.
-__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restrict__ part, int G, int ld,
-                                                          double* __restrict__ out)
+// out[j] = sum_b part[b * bs + j * cs], j < m.  grid: m.
+__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restrict__ part, int G, long long bs,
+                                                          long long cs, double* __restrict__ out)
 {
     __shared__ double red[kWaves];
     __shared__ double tot[1];
     const int j = blockIdx.x;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < G; b += kThreads) acc += part[(long long)b * ld + j];
+    for (int b = threadIdx.x; b < G; b += kThreads) acc += part[(long long)b * bs + j * cs];
     double v[1] = {acc};
     wg_sum_store<1>(v, tot, red);
     if (threadIdx.x == 0) out[j] = tot[0];
@@ -805,18 +967,21 @@ __global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restri
 // ---------------------------------------------------------------------------
 // finalize (one wave): equilibrium error of the iterate that went through F,
 // convergence / divergence / budget tests, and the Newton step on the
-// unstable subspace z' = z + (I - H)^{-1}(zeta - z) with the stored LU
-// factors (row pivots), giving the recombination coefficients d = z' - zeta
-// for the next xfwd (eps_next = xi + Z d).  The triangular solves run one row
-// at a time with the row's dot product spread over the wave.
+// unstable subspace z' = z + (I - H)^{-1}(zeta - z), applied as a product with
+// the inverse kept by k_factor, giving the recombination coefficients
+// d = z' - zeta for the next iterate eps_next = xi + Z d.
+// direct: z = Z^T eps was reduced into sums (after a basis change or at the
+// start of a solve); otherwise eps = xi_prev + Z d_prev was built from the
+// stored pair, so z = zeta_prev + G d_prev with the Gram matrix G = Z^T Z
+// (the same numbers without a second pass over the basis).
 // newton_only: skip the error bookkeeping (used after basis growth).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, const double* __restrict__ sums,
                                                  int p, int slot, int two_d, int newton_only, int err_mode,
-                                                 double* __restrict__ hist, int hist_cap)
+                                                 int direct, double* __restrict__ hist, int hist_cap)
 {
     __shared__ int sdone, snow, ssing;
-    __shared__ double r[kMaxP], b[kMaxP], y[kMaxP];
+    __shared__ double dprev[kMaxP], r[kMaxP];
     const int t = threadIdx.x;
     if (t == 0) {
         sdone = st->done;
@@ -847,15 +1012,22 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
         snow = st->done;
         ssing = st->singular;
     }
+    for (int j = t; j < p; j += 64) dprev[j] = st->d[j];
     __syncthreads();
     if (sdone) return;
-    for (int j = t; j < p; j += 64) {
-        const double ze = sums[1 + j], zz = sums[1 + p + j];
-        st->zeta[j] = ze;
-        st->z[j] = zz;
-        st->zeta_ring[slot][j] = ze;
-        r[j] = ze - zz;
-        b[j] = ze - zz;
+    for (int i = t; i < p; i += 64) {
+        const double ze = sums[1 + i];
+        double zz;
+        if (direct) {
+            zz = sums[1 + p + i];
+        } else {
+            zz = st->zeta[i];
+            for (int j = 0; j < p; ++j) zz += st->G[j * kMaxP + i] * dprev[j];
+        }
+        st->zeta[i] = ze;
+        st->z[i] = zz;
+        st->zeta_ring[slot][i] = ze;
+        r[i] = ze - zz;
     }
     __syncthreads();
     if (snow) return;
@@ -866,34 +1038,11 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
         }
         return;
     }
-    if (p == 0) return;
-    // stage the factors in LDS (row stride kMaxP + 1) before the dependent row sweeps
-    __shared__ double LUs[kMaxP * (kMaxP + 1)];
-    for (int i = 0; i < p; ++i)
-        for (int j = t; j < p; j += 64) LUs[i * (kMaxP + 1) + j] = st->LU[i * kMaxP + j];
-    if (t == 0)
-        for (int i = 0; i < p; ++i) {
-            const int q = st->piv[i];
-            const double tmp = b[i];
-            b[i] = b[q];
-            b[q] = tmp;
-        }
-    __syncthreads();
-    for (int i = 0; i < p; ++i) {  // unit lower triangle
-        double v = 0.0;
-        for (int j = t; j < i; j += 64) v += LUs[i * (kMaxP + 1) + j] * b[j];
-        v = wave_sum(v);
-        if (t == 0) b[i] -= v;
-        __syncthreads();
+    for (int i = t; i < p; i += 64) {
+        double y = 0.0;
+        for (int j = 0; j < p; ++j) y += st->AinvT[j * kMaxP + i] * r[j];
+        st->d[i] = y - r[i];  // z' - zeta = (z + y) - zeta
     }
-    for (int i = p - 1; i >= 0; --i) {  // upper triangle
-        double v = 0.0;
-        for (int j = i + 1 + t; j < p; j += 64) v += LUs[i * (kMaxP + 1) + j] * y[j];
-        v = wave_sum(v);
-        if (t == 0) y[i] = (b[i] - v) / LUs[i * (kMaxP + 1) + i];
-        __syncthreads();
-    }
-    for (int j = t; j < p; j += 64) st->d[j] = y[j] - r[j];  // z' - zeta = (z + y) - zeta
 }
 
 // Clear the stop flags and the step counter (a fresh map evaluation).
@@ -906,13 +1055,18 @@ __global__ void k_reset_state(DevState* __restrict__ st)
     }
 }
 
-// H gains row and column p: H[i][p] = col[i] (i <= p), H[p][j] = row[j] (j < p).
+// H gains row and column p: H[i][p] = col[i] (i <= p), H[p][j] = row[j] (j < p);
+// the Gram matrix gains gram[j] = <Z_p, Z_j> (j <= p) in row and column p.
 __global__ void k_border(DevState* __restrict__ st, const double* __restrict__ col, const double* __restrict__ row,
-                         int p)
+                         const double* __restrict__ gram, int p)
 {
     if (threadIdx.x != 0) return;
     for (int i = 0; i <= p; ++i) st->H[i * kMaxP + p] = col[i];
     for (int j = 0; j < p; ++j) st->H[p * kMaxP + j] = row[j];
+    for (int j = 0; j <= p; ++j) {
+        st->G[p * kMaxP + j] = gram[j];
+        st->G[j * kMaxP + p] = gram[j];
+    }
 }
 
 // LU factorisation with partial pivoting of I - H, one wave of 64 threads on
@@ -972,6 +1126,35 @@ __global__ __launch_bounds__(64) void k_factor(DevState* __restrict__ st, int p)
         st->singular = sing_s;
         st->p = p;
     }
+    if (sing_s) return;
+    // explicit inverse, one column per thread: L U x = P e_t.  perm[i] is the
+    // original row that the pivoting moved to position i.
+    __shared__ int perm[kMaxP];
+    __shared__ double X[kMaxP * kMaxP];
+    if (t == 0) {
+        for (int i = 0; i < p; ++i) perm[i] = i;
+        for (int c = 0; c < p; ++c) {
+            const int q = st->piv[c];
+            const int tmp = perm[c];
+            perm[c] = perm[q];
+            perm[q] = tmp;
+        }
+    }
+    __syncthreads();
+    if (t < p) {
+        for (int i = 0; i < p; ++i) {  // unit lower triangle
+            double v = perm[i] == t ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) v -= A[i * LD + k] * X[k * kMaxP + t];
+            X[i * kMaxP + t] = v;
+        }
+        for (int i = p - 1; i >= 0; --i) {  // upper triangle
+            double v = X[i * kMaxP + t];
+            for (int k = i + 1; k < p; ++k) v -= A[i * LD + k] * X[k * kMaxP + t];
+            X[i * kMaxP + t] = v / A[i * LD + i];
+        }
+        // column t of the inverse is row t of the transposed store
+        for (int i = 0; i < p; ++i) st->AinvT[t * kMaxP + i] = X[i * kMaxP + t];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -979,6 +1162,7 @@ __global__ __launch_bounds__(64) void k_factor(DevState* __restrict__ st, int p)
 // Each block covers kChunk voxels; partial sums are per block.
 // ---------------------------------------------------------------------------
 constexpr int kChunk = kThreads * 8;
+constexpr int kVecBlock = 16384;  // elements of the 6N-vector per block (element-parallel sums)
 
 // D1 = (xa - xb) - Z (za - zb);  D0 = (xb - xc) - Z (zb - zc) when xc != 0.
 // part[b][0..2] = D1.D1, D1.D0, D0.D0 (Frobenius).
@@ -1048,7 +1232,8 @@ __global__ __launch_bounds__(kThreads) void k_axpy_norm(double* __restrict__ y, 
 
 // RPM recombination eps = xi + sum_j d_j Z_j as a streaming pass: each thread
 // handles runs of VL consecutive elements; for a column, a wave reads one
-// contiguous kilobyte of its tile.
+// contiguous kilobyte of its tile.  Columns go in groups of 8 whose loads are
+// issued together; slots past p repeat column p - 1 with coefficient zero.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi, const T* __restrict__ Z, int p,
                                                         int zP, const double* __restrict__ dco,
@@ -1058,20 +1243,26 @@ __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi
     if (done && *done) return;
     constexpr int VL = 16 / sizeof(T);
     using V = typename Vec4<T>::type;
-    __shared__ T dj[kMaxP];
-    for (int j = threadIdx.x; j < p; j += kThreads) dj[j] = (T)dco[j];
+    __shared__ T dj[kMaxP + 8];
+    for (int j = threadIdx.x; j < kMaxP + 8; j += kThreads) dj[j] = j < p ? (T)dco[j] : T(0);
     __syncthreads();
     const long long e = ((long long)blockIdx.x * kThreads + threadIdx.x) * VL;
     if (e >= n) return;
     if (e + VL <= n) {
         V acc = *reinterpret_cast<const V*>(xi + e);
         T* a = reinterpret_cast<T*>(&acc);
-#pragma unroll 4
-        for (int j = 0; j < p; ++j) {
-            const V z = *reinterpret_cast<const V*>(Z + zix(e, j, zP));
-            const T* zs = reinterpret_cast<const T*>(&z);
+        const T* zt = Z + zix(e, 0, zP);  // column j at zt + j * kZTile
+        for (int g = 0; g < p; g += 8) {
+            V z[8];
 #pragma unroll
-            for (int u = 0; u < VL; ++u) a[u] += dj[j] * zs[u];
+            for (int u = 0; u < 8; ++u) z[u] = *reinterpret_cast<const V*>(zt + (long long)min(g + u, p - 1) * kZTile);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T* zs = reinterpret_cast<const T*>(&z[u]);
+                const T c = dj[g + u];
+#pragma unroll
+                for (int q = 0; q < VL; ++q) a[q] += c * zs[q];
+            }
         }
         *reinterpret_cast<V*>(eps + e) = acc;
     } else {
@@ -1083,19 +1274,18 @@ __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi
     }
 }
 
-// Column j of a tiled basis <-> a contiguous 6N-vector (times scale on the way in).
-template <typename T>
-__global__ void k_col_get(const T* __restrict__ Z, int j, int zP, T* __restrict__ out, long long n)
-{
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = Z[zix(i, j, zP)];
-}
-
+// Column j of the tiled basis from a contiguous 6N-vector (times scale), and
+// optionally the stored values again as a contiguous vector (copy).
 template <typename TI, typename T>
-__global__ void k_col_put(const TI* __restrict__ in, double scale, T* __restrict__ Z, int j, int zP, long long n)
+__global__ void k_col_put(const TI* __restrict__ in, double scale, T* __restrict__ Z, int j, int zP,
+                          T* __restrict__ copy, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) Z[zix(i, j, zP)] = (T)((double)in[i] * scale);
+    if (i < n) {
+        const T v = (T)((double)in[i] * scale);
+        Z[zix(i, j, zP)] = v;
+        if (copy) copy[i] = v;
+    }
 }
 
 template <typename TI, typename TO>
@@ -1115,8 +1305,8 @@ __global__ __launch_bounds__(kThreads) void k_residual_shift(const double* __res
     __shared__ double red[kWaves + 1];
     double acc[1] = {0.0};
     const long long L6 = 6 * N, N3 = 3 * N;
-    const long long e0 = (long long)blockIdx.x * kCdBlock;
-    for (int i = threadIdx.x; i < kCdBlock; i += kThreads) {
+    const long long e0 = (long long)blockIdx.x * kVecBlock;
+    for (int i = threadIdx.x; i < kVecBlock; i += kThreads) {
         const long long e = e0 + i;
         if (e >= L6) break;
         const double d = xi[e] - eps[e];

@@ -39,6 +39,10 @@ constexpr bool kSplitRecombine = RPM_SPLIT_RECOMBINE != 0;  // recombination as 
 #endif
 constexpr bool kYPipe = RPM_YPIPE != 0;        // software-pipelined y passes
 constexpr int kYPipeBlocks = RPM_YPIPE_BLOCKS;  // persistent grid of the pipelined y passes
+#ifndef RPM_TDOTS_BLOCKS
+#define RPM_TDOTS_BLOCKS 1024
+#endif
+constexpr int kTdotsBlocks = RPM_TDOTS_BLOCKS;  // grid cap of the basis products
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -91,7 +95,7 @@ struct Shapes {
     Geo g;
     Plan px, py, pr;
     size_t lds_x, lds_y, lds_g;
-    int G1, Gy, G3, Gg, Gp;
+    int G1, Gy, G3, Gg, Gp, Gq;
     bool ok;
 };
 
@@ -138,7 +142,9 @@ Shapes<T> make_shapes(const int32_t n[3])
     s.Gy = 6 * g.nh * (g.nz / g.tz);
     s.G3 = (npen + g.np - 1) / g.np;
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
-    s.Gp = (int)((6 * g.N + kCdBlock - 1) / kCdBlock);
+    s.Gp = (int)((6 * g.N + kVecBlock - 1) / kVecBlock);
+    const long long ntile = (6 * g.N + kZTile - 1) / kZTile;
+    s.Gq = (int)std::min<long long>(ntile, kTdotsBlocks);
     return s;
 }
 
@@ -191,8 +197,8 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.pmean = take(sizeof(double) * 6 * s.G1);
     L.perr = take(sizeof(double) * s.G3);
     L.pinc = take(sizeof(double) * s.G1);
-    L.pdots = take(sizeof(double) * 2 * L.ld * std::max(s.G1, s.Gp));
-    L.pg = take(sizeof(double) * (kMaxP + 4) * std::max(s.Gg, s.Gp));
+    L.pdots = take(sizeof(double) * 2 * L.ld * std::max(std::max(s.G1, s.Gp), s.Gq));
+    L.pg = take(sizeof(double) * (2 * kMaxP + 4) * std::max(std::max(s.Gg, s.Gp), s.Gq));
     L.sums = take(sizeof(double) * (2 * kMaxP + 8));
     L.gsum = take(sizeof(double) * (kMaxP + 8));
     for (int i = 0; i < 4; ++i) L.ring[i] = take(fT);
@@ -399,34 +405,49 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     c.check_launch();
 }
 
-int pow2_cols(int p)
+// Products <Z_j, a_f> (j < p) with the tiled basis: column-major partials
+// part[(f * ld + j) * G + b], one wave per group of 8 columns.
+template <typename TA, typename TZ, int NF>
+void launch_gdots(hipStream_t s, int G, const TA* a0, const TA* a1, const TZ* Z, int p, int zP, long long N,
+                  double* part, int ld)
 {
-    int pp = 8;
-    while (pp < p) pp *= 2;
-    return pp;
+    const int ng = (p + 7) / 8;
+    k_gdots<TA, TZ, NF><<<G, 64 * ng, 0, s>>>(a0, a1, Z, p, zP, N, part, ld);
 }
 
-// Products <Z_j, a> (and <Z_j, b> or <a, a>) for j < p, per block of kCdBlock elements.
-template <typename TA, typename TZ, bool TWO>
-void launch_coldots(hipStream_t s, int G, const TA* a, const TA* b, const TZ* Z, int p, int zP, long long N,
-                    double* part, int ld)
+// v <- v - sum_j coef_j Z_j, then the products <Z_j, v> (and, NRM, <v, v>):
+// row-major partials part[b * rs + j], norm at part[b * rs + kMaxP].
+template <typename TZ, bool NRM>
+void launch_update(hipStream_t s, int G, double* v, const TZ* Z, int p, int zP, const double* coef, long long N,
+                   double* part, int rs)
 {
-    k_coldots<TA, TZ, TWO><<<G, kThreads, 0, s>>>(a, b, Z, p, zP, pow2_cols(p), N, part, ld);
+    if (p <= 8)
+        k_tdots<double, TZ, 1, 8, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
+    else if (p <= 16)
+        k_tdots<double, TZ, 1, 16, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
+    else if (p <= 32)
+        k_tdots<double, TZ, 1, 32, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
+    else
+        k_tdots<double, TZ, 1, 64, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
 }
 
-// zeta_j = <Z_j, xi>, z_j = <Z_j, eps> partial sums for the Newton step.
+// zeta_j = <Z_j, xi> (and, direct, z_j = <Z_j, eps>) partial sums for the Newton step.
 template <typename T>
-void project(Ctx<T>& c, const T* xi, const T* eps, int p)
+void project(Ctx<T>& c, const T* xi, const T* eps, int p, bool direct)
 {
     if (p == 0) return;
     hipEvent_t ev;
     c.mark_begin(RPM_K_PROJECT, ev);
-    launch_coldots<T, T, true>(c.s, c.sh.Gp, xi, eps, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
-    c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * (2 + p));
+    if (direct)
+        launch_gdots<T, T, 2>(c.s, c.sh.Gq, xi, eps, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+    else
+        launch_gdots<T, T, 1>(c.s, c.sh.Gq, xi, nullptr, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+    c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * ((direct ? 2 : 1) + p));
 }
 
+// Reductions and the step bookkeeping after one F application (plus projections).
 template <typename T>
-void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, int G_dots, const int* done,
+void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, bool direct, const int* done,
                          int err_mode = 0)
 {
     hipEvent_t ev;
@@ -434,11 +455,12 @@ void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, int G_dots
     const double* perr = newton_only ? nullptr
                                      : (err_mode == 0 ? c.template at<double>(c.L.perr)
                                                       : c.template at<double>(c.L.pinc));
-    k_reduce_main<<<1 + 2 * p, kThreads, 0, c.s>>>(perr, err_mode == 0 ? c.sh.G3 : c.sh.G1, c.pdots(), G_dots,
-                                                   c.L.ld, p, c.sums(), done);
+    const int nf = direct ? 2 : 1;
+    k_reduce_main<<<1 + nf * p, kThreads, 0, c.s>>>(perr, err_mode == 0 ? c.sh.G3 : c.sh.G1, c.pdots(), c.sh.Gq,
+                                                    c.L.ld, p, c.sums(), done);
     c.mark_end(RPM_K_REDUCE, ev);
     c.mark_begin(RPM_K_FINAL, ev);
-    k_finalize<<<1, 64, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only, err_mode,
+    k_finalize<<<1, 64, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only, err_mode, direct ? 1 : 0,
                                  c.template at<double>(c.L.hist), (int)c.L.hist_cap);
     c.mark_end(RPM_K_FINAL, ev);
     c.check_launch();
@@ -454,9 +476,9 @@ bool sync_read(Ctx<T>& c, void* host, const void* dev, size_t bytes)
 }
 
 template <typename T>
-void reduce_cols(Ctx<T>& c, const double* part, int G, int ld, int m, double* out)
+void reduce_cols(Ctx<T>& c, const double* part, int G, long long bs, long long cs, int m, double* out)
 {
-    k_reduce_cols<<<m, kThreads, 0, c.s>>>(part, G, ld, out);
+    k_reduce_cols<<<m, kThreads, 0, c.s>>>(part, G, bs, cs, out);
 }
 
 // Initialise or re-validate the workspace header; uploads the tables.
@@ -546,7 +568,7 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
                                                c.pmax,
                                                c.st->zeta_ring[sa], c.st->zeta_ring[sb], c.st->zeta_ring[sc], D1,
                                                two ? D0 : nullptr, N, c.pg());
-    reduce_cols(c, c.pg(), Gg, 3, 3, c.gsum());
+    reduce_cols(c, c.pg(), Gg, 3, 1, 3, c.gsum());
     double gram[3];
     if (!sync_read(c, gram, c.gsum(), sizeof(gram))) return -1;
     const double T11 = std::sqrt(std::max(gram[0], 0.0));
@@ -555,7 +577,7 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     if (T11 > 0.0) {
         if (two) {
             k_axpy_norm<<<Gg, kThreads, 0, c.s>>>(D0, D1, gram[1] / gram[0], N, c.pg());
-            reduce_cols(c, c.pg(), Gg, 1, 1, c.gsum());
+            reduce_cols(c, c.pg(), Gg, 1, 1, 1, c.gsum());
             double n2;
             if (!sync_read(c, &n2, c.gsum(), sizeof(n2))) return -1;
             T22 = std::sqrt(std::max(n2, 0.0));
@@ -576,40 +598,42 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         k_convert<double, T><<<gb, 256, 0, c.s>>>(v, tmp, 1.0 / nrm, nel);
         project_compatible<T>(c, tmp, tmp2);
         k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
-        // two classical Gram-Schmidt passes against Z: coefficients, update, coefficients,
-        // update with the norm of the result
-        const int Gp = c.sh.Gp;
+        // two classical Gram-Schmidt passes against Z: coefficients; the update fused
+        // with the second coefficients; the second update fused with the norm
+        const int Gq = c.sh.Gq;
+        const int rs = 2 * kMaxP + 1;
         double* coef = c.gsum();
         double* coef2 = c.sums() + kMaxP + 2;
         if (p > 0) {
-            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), p + 1);
-            reduce_cols(c, c.pg(), Gp, p + 1, p, coef);
-            k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zb(), p, c.pmax, coef, N, c.pg());
-            launch_coldots<double, T, false>(c.s, Gp, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), p + 1);
-            reduce_cols(c, c.pg(), Gp, p + 1, p, coef2);
+            launch_gdots<double, T, 1>(c.s, Gq, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), kMaxP);
+            reduce_cols(c, c.pg(), Gq, 1, Gq, p, coef);
+            launch_update<T, false>(c.s, Gq, v, c.Zb(), p, c.pmax, coef, N, c.pg(), rs);
+            reduce_cols(c, c.pg(), Gq, rs, 1, p, coef2);
         }
-        k_axpy_basis<T><<<Gp, kThreads, 0, c.s>>>(v, c.Zb(), p, c.pmax, coef2, N, c.pg());
-        reduce_cols(c, c.pg(), Gp, 1, 1, coef + kMaxP);
+        launch_update<T, true>(c.s, Gq, v, c.Zb(), p, c.pmax, coef2, N, c.pg(), rs);
+        reduce_cols(c, c.pg() + kMaxP, Gq, rs, 1, 1, coef + kMaxP);
         double n2;
         if (!sync_read(c, &n2, coef + kMaxP, sizeof(n2))) return -1;
         const double vn = std::sqrt(std::max(n2, 0.0));
         if (!(vn > 1e-10)) continue;
         // store z_p in the basis and keep a contiguous copy (tmp) for the map
-        k_col_put<double, T><<<gb, 256, 0, c.s>>>(v, 1.0 / vn, c.Zb(), p, c.pmax, nel);
-        k_col_get<T><<<gb, 256, 0, c.s>>>(c.Zb(), p, c.pmax, tmp, nel);
-        // Jacobian-vector product w = F(z_p; E = 0): new column <z_i, w> (i <= p) of H
+        k_col_put<double, T><<<gb, 256, 0, c.s>>>(v, 1.0 / vn, c.Zb(), p, c.pmax, tmp, nel);
+        // Jacobian-vector product w = F(z_p; E = 0)
         run_F<T>(c, tmp, 0, nullptr, tmp, tmp2, OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
-        k_col_put<T, T><<<gb, 256, 0, c.s>>>(tmp2, 1.0, c.Wb(), p, c.pmax, nel);
+        k_col_put<T, T><<<gb, 256, 0, c.s>>>(tmp2, 1.0, c.Wb(), p, c.pmax, nullptr, nel);
+        // column p of H, <z_i, w> (i <= p), and of the Gram matrix, <z_i, z_p>, in one pass
         double* hcol = c.sums() + 1;
-        launch_coldots<T, T, false>(c.s, Gp, tmp2, nullptr, c.Zb(), p + 1, c.pmax, N, c.pg(), p + 2);
-        reduce_cols(c, c.pg(), Gp, p + 2, p + 1, hcol);
+        double* gram = c.sums() + kMaxP + 2;
+        launch_gdots<T, T, 2>(c.s, Gq, tmp2, tmp, c.Zb(), p + 1, c.pmax, N, c.pg(), kMaxP);
+        reduce_cols(c, c.pg(), Gq, 1, Gq, p + 1, hcol);
+        reduce_cols(c, c.pg() + (long long)kMaxP * Gq, Gq, 1, Gq, p + 1, gram);
         // new row: <z_p, w_j> for j < p
         double* row = c.gsum();
         if (p > 0) {
-            launch_coldots<T, T, false>(c.s, Gp, tmp, nullptr, c.Wb(), p, c.pmax, N, c.pg(), p + 1);
-            reduce_cols(c, c.pg(), Gp, p + 1, p, row);
+            launch_gdots<T, T, 1>(c.s, Gq, tmp, nullptr, c.Wb(), p, c.pmax, N, c.pg(), kMaxP);
+            reduce_cols(c, c.pg(), Gq, 1, Gq, p, row);
         }
-        k_border<<<1, 1, 0, c.s>>>(c.st, hcol, row, p);
+        k_border<<<1, 1, 0, c.s>>>(c.st, hcol, row, gram, p);
         ++p;
         ++added;
         ++*jvps;
@@ -688,8 +712,8 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
                                                                      N);
     }
     run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(1), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
-    if (rpm) project(c, c.ring(1), c.eps(), p);
-    reduce_and_finalize(c, rpm ? p : 0, 1, 0, c.sh.Gp, done, sp.err_mode);
+    if (rpm) project(c, c.ring(1), c.eps(), p, true);
+    reduce_and_finalize(c, rpm ? p : 0, 1, 0, true, done, sp.err_mode);
 
     int it = 1, nu = 0, nq = 0;
     const int check = std::max(1, o->check_every);
@@ -708,8 +732,8 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
                 nu = 0;
                 nq = 0;
                 // projections of the current pair (eps, xi) on the grown basis, Newton step
-                project(c, c.ring(it), c.eps(), p);
-                reduce_and_finalize(c, p, it, 1, c.sh.Gp, done, sp.err_mode);
+                project(c, c.ring(it), c.eps(), p, true);
+                reduce_and_finalize(c, p, it, 1, true, done, sp.err_mode);
             }
         }
         // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step
@@ -717,11 +741,11 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
         const T* xprev = c.ring(it - 1);
         if (rpm) {
             run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
-            project(c, c.ring(it), c.eps(), p);
+            project(c, c.ring(it), c.eps(), p, false);
         } else {
             run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
         }
-        reduce_and_finalize(c, rpm ? p : 0, it, 0, c.sh.Gp, done, sp.err_mode);
+        reduce_and_finalize(c, rpm ? p : 0, it, 0, false, done, sp.err_mode);
         ++nu;
         ++nq;
     }
@@ -761,7 +785,7 @@ rpm_status eval64(Ctx<double>& c64, DevState& hs)
 {
     k_reset_state<<<1, 1, 0, c64.s>>>(c64.st);
     run_F<double>(c64, c64.eps(), 0, nullptr, c64.eps(), c64.ring(1), OUT_XI, 0, DC_MEAN, c64.st->E, nullptr);
-    reduce_and_finalize(c64, 0, 1, 0, c64.sh.Gp, nullptr);
+    reduce_and_finalize(c64, 0, 1, 0, true, nullptr);
     if (!sync_read(c64, &hs, c64.st, sizeof(DevState))) return RPM_E_HIP;
     return RPM_OK;
 }
@@ -817,7 +841,7 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
         while (rs == RPM_OK && so.hs.status == 0 && res64 > o->tol && nref < o->refine) {
             // g = F64(eps64) - eps64, |g| in FP64
             k_residual_shift<T><<<c.sh.Gp, kThreads, 0, c.s>>>(c64.ring(1), c64.eps(), g32, N, c.pg());
-            reduce_cols(c, c.pg(), c.sh.Gp, 1, 1, c.gsum());
+            reduce_cols(c, c.pg(), c.sh.Gp, 1, 1, 1, c.gsum());
             double g2;
             if (!sync_read(c, &g2, c.gsum(), sizeof(g2))) return RPM_E_HIP;
             const double gnorm = std::sqrt(std::max(g2, 0.0));
@@ -944,7 +968,7 @@ rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_optio
     if (rs != RPM_OK) return rs;
     set_E(c, E);
     run_F<T>(c, (const T*)eps, 0, nullptr, (const T*)eps, (T*)xi, OUT_XI, 0, DC_MEAN, c.st->E, nullptr);
-    reduce_and_finalize(c, 0, 1, 0, c.sh.Gp, nullptr);
+    reduce_and_finalize(c, 0, 1, 0, true, nullptr);
     DevState hs;
     if (!sync_read(c, &hs, c.st, sizeof(hs))) return RPM_E_HIP;
     if (err) *err = hs.err;
