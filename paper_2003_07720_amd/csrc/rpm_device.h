@@ -32,6 +32,31 @@ __device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
 template <typename T, int S>
 __device__ __forceinline__ cx<T> cmul_si(cx<T> a) { return S > 0 ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x}; }
 
+// Division by a launch-invariant divisor d >= 1 as a multiply-high and a
+// shift (Granlund-Montgomery): with l = ceil(log2 d) and
+// m = floor(2^32 (2^l - d) / d) + 1, n / d = (mulhi(n, m) + n) >> l for
+// 0 <= n < 2^31.  Index arithmetic in the pencil kernels uses it in place of
+// the integer division sequence.
+struct FDiv {
+    uint32_t d, m;
+    int l;
+    __host__ __device__ __forceinline__ int div(int n) const
+    {
+        const uint32_t t = (uint32_t)(((uint64_t)(uint32_t)n * m) >> 32);
+        return (int)((t + (uint32_t)n) >> l);
+    }
+};
+
+inline FDiv make_fdiv(int d)
+{
+    FDiv f;
+    f.d = (uint32_t)d;
+    f.l = 0;
+    while ((1ull << f.l) < (unsigned long long)d) ++f.l;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << f.l) - (unsigned long long)d)) / (unsigned long long)d + 1);
+    return f;
+}
+
 // Transform lengths are products of the radices of one plan.
 struct Plan {
     int n;
@@ -155,8 +180,15 @@ __device__ __forceinline__ void dftR(cx<T>* v)
     else dft16<T, D>(v);
 }
 
+// LDS layout of the pencils: element i of a sequence sits at lpad(i) (one
+// spare slot after every 32 elements) and sequences are lrow(n) slots apart.
+// The spare slots break the power-of-two strides of the Stockham writes and
+// of column-wise fills, which otherwise land on a few LDS banks.
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 5); }
+__host__ __device__ constexpr int lrow(int n) { return n + (n >> 5) + 1; }
+
 // One Stockham stage over nseq sequences of length n held in LDS with row
-// stride ss (complex elements).  Ns = product of the radices already applied.
+// stride ss.  Ns = product of the radices already applied.
 // tw[e] = exp(-2 pi i e / n), e in [0, n).
 template <typename T, int R, int D>
 __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns,
@@ -172,7 +204,7 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
         cx<T>* out = dst + s * ss;
         cx<T> v[R];
 #pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = in[j + q * nb];
+        for (int q = 0; q < R; ++q) v[q] = in[lpad(j + q * nb)];
         const int k = j % Ns;
         if (Ns > 1) {
 #pragma unroll
@@ -185,7 +217,59 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
         dftR<T, R, D>(v);
         const int o = (j - k) * R + k;
 #pragma unroll
-        for (int q = 0; q < R; ++q) out[o + q * Ns] = v[q];
+        for (int q = 0; q < R; ++q) out[lpad(o + q * Ns)] = v[q];
+    }
+}
+
+// The same stage with the length and the stage position fixed at compile time
+// (power-of-two lengths): index arithmetic reduces to shifts and masks.
+template <typename T, int R, int D, int N, int NS>
+__device__ __forceinline__ void fft_stage_ct(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int nseq,
+                                             int ss, const cx<T>* __restrict__ tw)
+{
+    constexpr int nb = N / R;
+    constexpr int tws = N / (NS * R);
+    const int total = nb * nseq;
+    for (int g = threadIdx.x; g < total; g += kThreads) {
+        const int s = g / nb;
+        const int j = g & (nb - 1);
+        const cx<T>* in = src + s * ss;
+        cx<T>* out = dst + s * ss;
+        cx<T> v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = in[lpad(j + q * nb)];
+        const int k = j & (NS - 1);
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int q = 1; q < R; ++q) {
+                cx<T> w = tw[q * k * tws];
+                if (D > 0) w.y = -w.y;
+                v[q] = cmul(v[q], w);
+            }
+        }
+        dftR<T, R, D>(v);
+        const int o = (j - k) * R + k;
+#pragma unroll
+        for (int q = 0; q < R; ++q) out[lpad(o + q * NS)] = v[q];
+    }
+}
+
+// Radix sequence of a power-of-two length: radix 16 while possible, then one
+// stage of 8, 4 or 2 (the host plan builds the same sequence).
+constexpr int ct_log2(int n) { return n <= 1 ? 0 : 1 + ct_log2(n / 2); }
+constexpr int ct_nst(int n) { return ct_log2(n) / 4 + (ct_log2(n) % 4 ? 1 : 0); }
+constexpr int ct_rad(int n, int st) { return st < ct_log2(n) / 4 ? 16 : (1 << (ct_log2(n) % 4)); }
+
+template <typename T, int D, int N, int ST, int NS>
+__device__ __forceinline__ cx<T>* ct_stages(cx<T>* src, cx<T>* dst, int nseq, int ss, const cx<T>* tw)
+{
+    if constexpr (ST == ct_nst(N)) {
+        return src;
+    } else {
+        constexpr int R = ct_rad(N, ST);
+        fft_stage_ct<T, R, D, N, NS>(src, dst, nseq, ss, tw);
+        __syncthreads();
+        return ct_stages<T, D, N, ST + 1, NS * R>(dst, src, nseq, ss, tw);
     }
 }
 
@@ -195,6 +279,7 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
 template <typename T, int D>
 __device__ cx<T>* lds_fft(cx<T>* a, cx<T>* b, const Plan& pl, int nseq, int ss, const cx<T>* tw)
 {
+    if (pl.n == 128) return ct_stages<T, D, 128, 0, 1>(a, b, nseq, ss, tw);
     int Ns = 1;
     cx<T>* src = a;
     cx<T>* dst = b;

@@ -32,12 +32,13 @@ struct Geo {
     int tz;                // z columns per y-pass tile
     int np;                // pencils per gamma tile
     int two_d;
+    FDiv fnx, fny, fnh, fty, ftz, frow;  // divisions by nx, ny, nh, ty, tz and the gamma row length
 };
 
 // Basis storage: Z (and W = F_u Z) in tiles of kZTile consecutive elements of
 // the 6N-vector; tile t holds its slice of all P column slots contiguously, so
 // element e of column j sits at zix(e, j, P).  Per-voxel recombination and the
-// lane-per-column projections then read long contiguous runs.
+// basis products then read contiguous kilobyte slices.
 constexpr int kZTile = 256;
 __host__ __device__ __forceinline__ long long zix(long long e, int j, int P)
 {
@@ -98,7 +99,7 @@ struct MaxV<double> { static constexpr int v = 4; };
 
 // ---------------------------------------------------------------------------
 // x-forward: recombination + constitutive law + R2C FFT along x.
-// grid: nz * (ny / ty) blocks.  LDS: 2 * ty * (nx+1) + nx complex + reduction.
+// grid: nz * (ny / ty) blocks.  LDS: 2 * ty * lrow(nx) + nx complex + reduction.
 // ---------------------------------------------------------------------------
 template <typename T, bool VEC>
 __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const T* __restrict__ Z, int p, int zP,
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MV = MaxV<T>::v;
-    const int nx = g.nx, ty = g.ty, ss = nx + 1;
+    const int nx = g.nx, ty = g.ty, ss = lrow(nx);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
     cx<T>* tw = B + ty * ss;
@@ -211,10 +212,10 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
         for (int i = 0; i < MV / VL; ++i) {
             const int v0 = (threadIdx.x + i * kThreads) * VL;
             if (v0 < nvox) {
-                const int r = v0 / nx;
+                const int r = g.fnx.div(v0);
                 const int x = v0 - r * nx;
 #pragma unroll
-                for (int u = 0; u < VL; ++u) A[r * ss + x + u] = cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]};
+                for (int u = 0; u < VL; ++u) A[r * ss + lpad(x + u)] = cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]};
             }
         }
         __syncthreads();
@@ -223,10 +224,10 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
         cx<T>* outa = S1 + (long long)(2 * q) * g.nspec;
         cx<T>* outb = S1 + (long long)(2 * q + 1) * g.nspec;
         for (int t = threadIdx.x; t < nh * ty; t += kThreads) {
-            const int r = t % ty;
-            const int k = t / ty;
-            const cx<T> X = R[r * ss + k];
-            const cx<T> Yc = cconj(R[r * ss + (k == 0 ? 0 : nx - k)]);
+            const int k = g.fty.div(t);
+            const int r = t - k * ty;
+            const cx<T> X = R[r * ss + lpad(k)];
+            const cx<T> Yc = cconj(R[r * ss + lpad(k == 0 ? 0 : nx - k)]);
             const cx<T> s = cadd(X, Yc);
             const cx<T> d = csub(X, Yc);
             const long long o = ((long long)k * g.nz + z) * g.ny + y0 + r;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(const cx<T>* __restrict__ S1,
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ny = g.ny, tz = g.tz, ss = ny + 1;
+    const int ny = g.ny, tz = g.tz, ss = lrow(ny);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + tz * ss;
     cx<T>* tw = B + tz * ss;
@@ -261,17 +262,17 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(const cx<T>* __restrict__ S1,
     for (int i = threadIdx.x; i < ny; i += kThreads) tw[i] = twy[i];
     const cx<T>* src = S1 + (long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny;
     for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
-        const int r = t / ny;
+        const int r = g.fny.div(t);
         const int y = t - r * ny;
-        A[r * ss + y] = src[t];
+        A[r * ss + lpad(y)] = src[t];
     }
     __syncthreads();
     const cx<T>* R = lds_fft<T, -1>(A, B, py, tz, ss, tw);
     cx<T>* dst = S2 + (long long)c * g.nspec;
     for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
-        const int r = t % tz;
-        const int ky = t / tz;
-        dst[((long long)ky * g.nh + kx) * g.nz + z0 + r] = R[r * ss + ky];
+        const int ky = g.ftz.div(t);
+        const int r = t - ky * tz;
+        dst[((long long)ky * g.nh + kx) * g.nz + z0 + r] = R[r * ss + lpad(ky)];
     }
 }
 
@@ -279,13 +280,13 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(const cx<T>* __restrict__ S1,
 // keeps its share of the next tile in registers (loads in flight during the
 // current tile's LDS transform and stores).  PT bounds tz * ny / kThreads.
 template <typename T, int D, int PT>
-__global__ __launch_bounds__(kThreads) void k_ypipe(const cx<T>* __restrict__ Sin, cx<T>* __restrict__ Sout, Geo g,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_ypipe(const cx<T>* __restrict__ Sin, cx<T>* __restrict__ Sout, Geo g,
                                                     Plan py, const cx<T>* __restrict__ twy, int ntiles,
                                                     const int* __restrict__ done)
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ny = g.ny, tz = g.tz, ss = ny + 1;
+    const int ny = g.ny, tz = g.tz, ss = lrow(ny);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + tz * ss;
     cx<T>* tw = B + tz * ss;
@@ -308,7 +309,7 @@ __global__ __launch_bounds__(kThreads) void k_ypipe(const cx<T>* __restrict__ Si
                 if (D < 0) {
                     pre[u] = Sin[(long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny + e];
                 } else {
-                    const int r = e % tz, ky = e / tz;
+                    const int ky = g.ftz.div(e), r = e - ky * tz;
                     pre[u] = Sin[(long long)c * g.nspec + ((long long)ky * g.nh + kx) * g.nz + z0 + r];
                 }
             }
@@ -323,11 +324,11 @@ __global__ __launch_bounds__(kThreads) void k_ypipe(const cx<T>* __restrict__ Si
             const int e = threadIdx.x + u * kThreads;
             if (e < nel) {
                 if (D < 0) {
-                    const int r = e / ny, y = e - (e / ny) * ny;
-                    A[r * ss + y] = pre[u];
+                    const int r = g.fny.div(e), y = e - r * ny;
+                    A[r * ss + lpad(y)] = pre[u];
                 } else {
-                    const int r = e % tz, ky = e / tz;
-                    A[r * ss + ky] = pre[u];
+                    const int ky = g.ftz.div(e), r = e - ky * tz;
+                    A[r * ss + lpad(ky)] = pre[u];
                 }
             }
         }
@@ -344,14 +345,14 @@ __global__ __launch_bounds__(kThreads) void k_ypipe(const cx<T>* __restrict__ Si
         if (D < 0) {
             cx<T>* dst = Sout + (long long)c * g.nspec;
             for (int e = threadIdx.x; e < nel; e += kThreads) {
-                const int r = e % tz, ky = e / tz;
-                dst[((long long)ky * g.nh + kx) * g.nz + z0 + r] = R[r * ss + ky];
+                const int ky = g.ftz.div(e), r = e - ky * tz;
+                dst[((long long)ky * g.nh + kx) * g.nz + z0 + r] = R[r * ss + lpad(ky)];
             }
         } else {
             cx<T>* dst = Sout + (long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny;
             for (int e = threadIdx.x; e < nel; e += kThreads) {
-                const int r = e / ny, y = e - r * ny;
-                dst[e] = R[r * ss + y];
+                const int r = g.fny.div(e), y = e - r * ny;
+                dst[e] = R[r * ss + lpad(y)];
             }
         }
     }
@@ -367,7 +368,7 @@ __global__ __launch_bounds__(kThreads) void k_yinv(const cx<T>* __restrict__ S2,
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int ny = g.ny, tz = g.tz, ss = ny + 1;
+    const int ny = g.ny, tz = g.tz, ss = lrow(ny);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + tz * ss;
     cx<T>* tw = B + tz * ss;
@@ -381,17 +382,17 @@ __global__ __launch_bounds__(kThreads) void k_yinv(const cx<T>* __restrict__ S2,
     for (int i = threadIdx.x; i < ny; i += kThreads) tw[i] = twy[i];
     const cx<T>* src = S2 + (long long)c * g.nspec;
     for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
-        const int r = t % tz;
-        const int ky = t / tz;
-        A[r * ss + ky] = src[((long long)ky * g.nh + kx) * g.nz + z0 + r];
+        const int ky = g.ftz.div(t);
+        const int r = t - ky * tz;
+        A[r * ss + lpad(ky)] = src[((long long)ky * g.nh + kx) * g.nz + z0 + r];
     }
     __syncthreads();
     const cx<T>* R = lds_fft<T, +1>(A, B, py, tz, ss, tw);
     cx<T>* dst = S1 + (long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny;
     for (int t = threadIdx.x; t < tz * ny; t += kThreads) {
-        const int r = t / ny;
+        const int r = g.fny.div(t);
         const int y = t - r * ny;
-        dst[t] = R[r * ss + y];
+        dst[t] = R[r * ss + lpad(y)];
     }
 }
 
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
     extern __shared__ __align__(16) unsigned char smem[];
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
-    const int ss = nrow + 1;
+    const int ss = lrow(nrow);
     const int p0 = blockIdx.x * g.np;
     const int npl = min(g.np, npen - p0);
     const int nseq = 6 * npl;
@@ -453,9 +454,9 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
     for (int c = 0; c < 6; ++c) {
         const cx<T>* src = S + (long long)c * g.nspec + (long long)p0 * nrow;
         for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
-            const int pl = t / nrow;
+            const int pl = g.frow.div(t);
             const int i = t - pl * nrow;
-            A[(c * npl + pl) * ss + i] = src[t];
+            A[(c * npl + pl) * ss + lpad(i)] = src[t];
         }
     }
     // block 0 holds the k = 0 frequency: finish <eps> from the xfwd partials
@@ -477,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
     const double imu = 1.0 / mu0;
     double esum = 0.0;
     for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
-        const int pl = t / nrow;
+        const int pl = g.frow.div(t);
         const int i = t - pl * nrow;
         const int pen = p0 + pl;
         int kx, ky, kz;
@@ -486,13 +487,13 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
             ky = i;
             kz = 0;
         } else {
-            ky = pen / g.nh;
+            ky = g.fnh.div(pen);
             kx = pen - ky * g.nh;
             kz = i;
         }
         cx<T> s[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s[c] = R[(c * npl + pl) * ss + i];
+        for (int c = 0; c < 6; ++c) s[c] = R[(c * npl + pl) * ss + lpad(i)];
         cx<T> o[6];
         if (kx == 0 && ky == 0 && kz == 0) {
             const double Nd = (double)g.N;
@@ -527,16 +528,16 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
             o[5] = csub(cadd(cscale(sy, hm * n0), cscale(sx, hm * n1)), cscale(a, cc * n0 * n1));
         }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) R[(c * npl + pl) * ss + i] = o[c];
+        for (int c = 0; c < 6; ++c) R[(c * npl + pl) * ss + lpad(i)] = o[c];
     }
     __syncthreads();
     const cx<T>* Q = lds_fft<T, +1>(R, R == A ? B : A, pr, nseq, ss, tw);
     for (int c = 0; c < 6; ++c) {
         cx<T>* dst = S + (long long)c * g.nspec + (long long)p0 * nrow;
         for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
-            const int pl = t / nrow;
+            const int pl = g.frow.div(t);
             const int i = t - pl * nrow;
-            dst[t] = Q[(c * npl + pl) * ss + i];
+            dst[t] = Q[(c * npl + pl) * ss + lpad(i)];
         }
     }
     double ev[1] = {esum};
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MV = MaxV<T>::v;
-    const int nx = g.nx, ty = g.ty, ss = nx + 1, nh = g.nh;
+    const int nx = g.nx, ty = g.ty, ss = lrow(nx), nh = g.nh;
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
     cx<T>* tw = B + ty * ss;
@@ -575,8 +576,8 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
         const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
         const cx<T>* inb = S1 + (long long)(2 * q + 1) * g.nspec;
         for (int t = threadIdx.x; t < nh * ty; t += kThreads) {
-            const int r = t % ty;
-            const int k = t / ty;
+            const int k = g.fty.div(t);
+            const int r = t - k * ty;
             const long long o = ((long long)k * g.nz + z) * g.ny + y0 + r;
             cx<T> a = ina[o];
             cx<T> b = inb[o];
@@ -585,8 +586,8 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                 a.y = T(0);
                 b.y = T(0);
             }
-            A[r * ss + k] = cx<T>{a.x - b.y, a.y + b.x};
-            if (!selfc) A[r * ss + nx - k] = cx<T>{a.x + b.y, b.x - a.y};
+            A[r * ss + lpad(k)] = cx<T>{a.x - b.y, a.y + b.x};
+            if (!selfc) A[r * ss + lpad(nx - k)] = cx<T>{a.x + b.y, b.x - a.y};
         }
         __syncthreads();
         const cx<T>* R = lds_fft<T, +1>(A, B, px, ty, ss, tw);
@@ -595,9 +596,9 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
         for (int i = 0; i < MV; ++i) {
             const int v = threadIdx.x + i * kThreads;
             if (v < nvox) {
-                const int r = v / nx;
+                const int r = g.fnx.div(v);
                 const int x = v - r * nx;
-                const cx<T> val = R[r * ss + x];
+                const cx<T> val = R[r * ss + lpad(x)];
                 const long long gi = base + v;
                 const T ta = val.x * invN, tb = val.y * invN;
                 if (out_mode == OUT_XI) {

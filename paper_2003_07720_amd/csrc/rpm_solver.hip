@@ -118,23 +118,29 @@ Shapes<T> make_shapes(const int32_t n[3])
     int tycap = std::min(128 / wsz, MV * kThreads / g.nx);
     if (tycap < 1) s.ok = false;
     g.ty = largest_divisor_leq(g.ny, std::max(tycap, 1));
-    while (g.ty > 1 && (size_t)(2 * g.ty * (g.nx + 1) + g.nx) * wsz + 80 * 8 > (size_t)kLdsCap)
+    while (g.ty > 1 && (size_t)(2 * g.ty * lrow(g.nx) + g.nx) * wsz + 80 * 8 > (size_t)kLdsCap)
         g.ty = largest_divisor_leq(g.ny, g.ty - 1);
-    s.lds_x = (size_t)(2 * g.ty * (g.nx + 1) + g.nx) * wsz + 80 * 8;
+    s.lds_x = (size_t)(2 * g.ty * lrow(g.nx) + g.nx) * wsz + 80 * 8;
     // y passes: tz columns of ny
     g.tz = largest_divisor_leq(g.nz, 128 / wsz);
-    while (g.tz > 1 && (size_t)(2 * g.tz * (g.ny + 1) + g.ny) * wsz > (size_t)kLdsCap)
+    while (g.tz > 1 && (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz > (size_t)kLdsCap)
         g.tz = largest_divisor_leq(g.nz, g.tz - 1);
-    s.lds_y = (size_t)(2 * g.tz * (g.ny + 1) + g.ny) * wsz;
+    s.lds_y = (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz;
     // gamma pass: np pencils x 6 components along the last axis
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
     int np = 16;
-    while (np > 1 && (size_t)(12 * np * (nrow + 1) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
+    while (np > 1 && (size_t)(12 * np * lrow(nrow) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
     g.np = np;
-    s.lds_g = (size_t)(12 * np * (nrow + 1) + nrow) * wsz + 80 * 8;
+    s.lds_g = (size_t)(12 * np * lrow(nrow) + nrow) * wsz + 80 * 8;
     if (s.lds_x > (size_t)kLdsCap || s.lds_y > (size_t)kLdsCap || s.lds_g > (size_t)kLdsCap) s.ok = false;
     if (g.ty * g.nx > MV * kThreads) s.ok = false;
+    g.fnx = make_fdiv(g.nx);
+    g.fny = make_fdiv(g.ny);
+    g.fnh = make_fdiv(g.nh);
+    g.fty = make_fdiv(g.ty);
+    g.ftz = make_fdiv(g.tz);
+    g.frow = make_fdiv(nrow);
     s.px = make_plan(g.nx);
     s.py = make_plan(g.ny);
     s.pr = make_plan(nrow);
