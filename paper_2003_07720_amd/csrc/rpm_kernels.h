@@ -630,18 +630,8 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
 }
 
 // ---------------------------------------------------------------------------
-// Products with the tiled basis Z.  A wave owns whole tiles of kZTile
-// elements; lane l holds elements 4l .. 4l+3 of its tile, so the slice of
-// column j in that tile is one coalesced read (1 KB for float), and the lane
-// keeps one FP64 accumulator per column and field:
-//   part[b * rs + f * ld + j] = sum_e w(e) Z_j[e] a_f[e]      (j < p, f < NF)
-// w(e) = 1 on the normal components (e < 3N), 2 on the shear ones.
-// UPD: a_0 <- a_0 - sum_j coef_j Z_j first (written back; the products are
-//      then those of the updated field).
-// NRM: part[b * rs + NF * ld] = sum_e w(e) a_0[e]^2 (after the update).
-// PC is a compile-time bound on p (accumulators live in registers).  Block b
-// takes tiles b * kWaves + wave + k * gridDim.x * kWaves: a fixed assignment,
-// so the sums are reproducible.
+// Products with the tiled basis Z (Frobenius weights: 1 on the normal
+// components e < 3N, 2 on the shear ones).
 // ---------------------------------------------------------------------------
 // Four consecutive elements as raw 16- or 32-byte loads, converted on use.
 template <typename T>
@@ -773,6 +763,15 @@ __global__ __launch_bounds__(512) void k_gdots(const TA* __restrict__ a0, const 
             if (lane == 0 && u < nj) part[(long long)(f * ld + j0 + u) * gridDim.x + blockIdx.x] = sum;
         }
 }
+
+// Update-and-project (Gram-Schmidt step) k_tdots: a wave owns whole tiles;
+// lane l holds elements 4l .. 4l+3 of its tile and all p columns of it, so
+// the update a_0 <- a_0 - sum_j coef_j Z_j (UPD, written back) is complete in
+// registers before the products
+//   part[b * rs + f * ld + j] = sum_e w(e) Z_j[e] a_f[e]      (j < p, f < NF)
+// and, NRM, part[b * rs + NF * ld] = sum_e w(e) a_0[e]^2 (after the update).
+// PC bounds p at compile time (one FP64 accumulator per column in registers).
+// Block b takes tiles b * kWaves + wave + k * gridDim.x * kWaves.
 
 // One tile of k_tdots for one lane: elements e0 .. e0+3 (FULL: all inside the
 // vector, no guards).
@@ -1166,7 +1165,10 @@ constexpr int kChunk = kThreads * 8;
 constexpr int kVecBlock = 16384;  // elements of the 6N-vector per block (element-parallel sums)
 
 // D1 = (xa - xb) - Z (za - zb);  D0 = (xb - xc) - Z (zb - zc) when xc != 0.
-// part[b][0..2] = D1.D1, D1.D0, D0.D0 (Frobenius).
+// part[b][0..2] = D1.D1, D1.D0, D0.D0 (Frobenius).  Each thread takes 4
+// consecutive elements of the 6N-vector (one tile slice) and the columns in
+// groups of 8 whose loads are issued together (slots past p repeat column
+// p - 1 with coefficient zero).  grid: ceil(6N / (4 kThreads)).
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ xa, const T* __restrict__ xb,
                                                           const T* __restrict__ xc, const T* __restrict__ Z, int p,
@@ -1178,33 +1180,70 @@ __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ 
                                                           double* __restrict__ part)
 {
     __shared__ double red[kWaves * 3 + 3];
-    __shared__ double c1[kMaxP], c0[kMaxP];
-    for (int j = threadIdx.x; j < p; j += kThreads) {
-        c1[j] = za[j] - zb[j];
-        c0[j] = xc ? (zb[j] - zc[j]) : 0.0;
+    __shared__ double c1[kMaxP + 8], c0[kMaxP + 8];
+    for (int j = threadIdx.x; j < kMaxP + 8; j += kThreads) {
+        c1[j] = j < p ? za[j] - zb[j] : 0.0;
+        c0[j] = (j < p && xc) ? (zb[j] - zc[j]) : 0.0;
     }
     __syncthreads();
     double acc[3] = {0.0, 0.0, 0.0};
-    const long long b0 = (long long)blockIdx.x * kChunk;
-    for (int i = 0; i < kChunk / kThreads; ++i) {
-        const long long v = b0 + threadIdx.x + i * kThreads;
-        if (v >= N) break;
+    const long long L6 = 6 * N, N3 = 3 * N;
+    const long long e0 = ((long long)blockIdx.x * kThreads + threadIdx.x) * 4;
+    if (e0 < L6) {
+        const bool full = e0 + 4 <= L6;
+        double d1[4], d0[4], t[4];
+        Raw4<T> r;
+        if (full) r.load(xa + e0);
+        else r.load_tail(xa + e0, e0, L6);
+        r.get(d1);
+        if (full) r.load(xb + e0);
+        else r.load_tail(xb + e0, e0, L6);
+        r.get(t);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            const long long o = c * N + v;
-            double d1 = (double)xa[o] - (double)xb[o];
-            double d0 = xc ? ((double)xb[o] - (double)xc[o]) : 0.0;
-            for (int j = 0; j < p; ++j) {
-                const double zz = (double)Z[zix(o, j, zP)];
-                d1 -= c1[j] * zz;
-                d0 -= c0[j] * zz;
+        for (int q = 0; q < 4; ++q) {
+            d1[q] -= t[q];
+            d0[q] = t[q];
+        }
+        if (xc) {
+            if (full) r.load(xc + e0);
+            else r.load_tail(xc + e0, e0, L6);
+            r.get(t);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d0[q] -= t[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) d0[q] = 0.0;
+        }
+        const T* zt = Z + zix(e0, 0, zP);  // column j at zt + j * kZTile
+        for (int g = 0; g < p; g += 8) {
+            Raw4<T> raw[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T* zc_ = zt + (long long)min(g + u, p - 1) * kZTile;
+                if (full) raw[u].load(zc_);
+                else raw[u].load_tail(zc_, e0, L6);
             }
-            D1[o] = d1;
-            if (xc) D0[o] = d0;
-            const double w = frob_w(c);
-            acc[0] += w * d1 * d1;
-            acc[1] += w * d1 * d0;
-            acc[2] += w * d0 * d0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                double z[4];
+                raw[u].get(z);
+                const double a1 = c1[g + u], a0 = c0[g + u];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    d1[q] -= a1 * z[q];
+                    d0[q] -= a0 * z[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!full && e0 + q >= L6) continue;
+            D1[e0 + q] = d1[q];
+            if (xc) D0[e0 + q] = d0[q];
+            const double w = e0 + q < N3 ? 1.0 : 2.0;
+            acc[0] += w * d1[q] * d1[q];
+            acc[1] += w * d1[q] * d0[q];
+            acc[2] += w * d0[q] * d0[q];
         }
     }
     wg_sum_store<3>(acc, part + (long long)blockIdx.x * 3, red);

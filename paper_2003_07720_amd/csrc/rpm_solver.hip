@@ -129,7 +129,7 @@ Shapes<T> make_shapes(const int32_t n[3])
     // gamma pass: np pencils x 6 components along the last axis
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
-    int np = 16;
+    int np = 2;  // two pencils (x 6 components) per gamma tile: more resident tiles per CU
     while (np > 1 && (size_t)(12 * np * lrow(nrow) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
     g.np = np;
     s.lds_g = (size_t)(12 * np * lrow(nrow) + nrow) * wsz + 80 * 8;
@@ -204,7 +204,9 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.perr = take(sizeof(double) * s.G3);
     L.pinc = take(sizeof(double) * s.G1);
     L.pdots = take(sizeof(double) * 2 * L.ld * std::max(std::max(s.G1, s.Gp), s.Gq));
-    L.pg = take(sizeof(double) * (2 * kMaxP + 4) * std::max(std::max(s.Gg, s.Gp), s.Gq));
+    const long long Gd = (6 * g.N + 4 * kThreads - 1) / (4 * kThreads);  // k_growth_diff blocks (3 partials each)
+    L.pg = take(sizeof(double) * std::max((size_t)(2 * kMaxP + 4) * std::max(std::max(s.Gg, s.Gp), s.Gq),
+                                          (size_t)(3 * Gd)));
     L.sums = take(sizeof(double) * (2 * kMaxP + 8));
     L.gsum = take(sizeof(double) * (kMaxP + 8));
     for (int i = 0; i < 4; ++i) L.ring[i] = take(fT);
@@ -570,11 +572,12 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     const bool two = nq >= 3;
     hipEvent_t ev;
     c.mark_begin(RPM_K_GROWTH, ev);
-    k_growth_diff<T><<<Gg, kThreads, 0, c.s>>>(c.ring(sa), c.ring(sb), two ? c.ring(sc) : nullptr, c.Zb(), p,
+    const int Gd = (int)((6 * N + 4 * kThreads - 1) / (4 * kThreads));
+    k_growth_diff<T><<<Gd, kThreads, 0, c.s>>>(c.ring(sa), c.ring(sb), two ? c.ring(sc) : nullptr, c.Zb(), p,
                                                c.pmax,
                                                c.st->zeta_ring[sa], c.st->zeta_ring[sb], c.st->zeta_ring[sc], D1,
                                                two ? D0 : nullptr, N, c.pg());
-    reduce_cols(c, c.pg(), Gg, 3, 1, 3, c.gsum());
+    reduce_cols(c, c.pg(), Gd, 3, 1, 3, c.gsum());
     double gram[3];
     if (!sync_read(c, gram, c.gsum(), sizeof(gram))) return -1;
     const double T11 = std::sqrt(std::max(gram[0], 0.0));
