@@ -14,7 +14,12 @@ Each wrapper names the passage of the paper it follows:
   (``scheme="rpm"``) for one mean strain E (Sec. 2: the average strain is
   given);
 * :func:`effective_tensor` -- the effective response (title; Sec. 1: given
-  the average strain, the fields in the cell) as one solve per unit load case.
+  the average strain, the fields in the cell) as one solve per unit load case;
+* ``map="polarization"`` in :func:`fmap` / :func:`solve` -- the polarization
+  iteration of Algorithm 3 (Accelerated FFT for alpha = beta = 2, Sec. 5.5) in
+  place of F, with the sign of the C0 term of s_b corrected (s_b = alpha sigma
+  - beta C0:eps); :func:`polarization_reduced` -- the form it takes on
+  compatible fields of mean E, eps + alpha (C + C0)^{-1} C0 (F(eps) - eps).
 """
 from __future__ import annotations
 
@@ -62,10 +67,11 @@ def _load():
         lib.orc_gamma_apply.argtypes = [dp, d, d, dp, dp]
         lib.orc_stress.argtypes = [ctypes.c_long, u8p, dp, dp, dp]
         lib.orc_project_compatible.argtypes = [i, i, i, d, d, dp]
-        lib.orc_fmap.argtypes = [i, i, i, u8p, dp, d, d, dp, dp, dp, dp, dp]
+        lib.orc_fmap.argtypes = [i, i, i, u8p, dp, d, d, dp, dp, dp, dp, dp, i, d, d]
         lib.orc_fmap.restype = d
+        lib.orc_polarization_reduced.argtypes = [i, i, i, u8p, dp, d, d, dp, dp, d, dp]
         lib.orc_solve.argtypes = [i, i, i, u8p, dp, d, d, dp, i, d, i, i, i, d, ip, i, dp, dp, dp, dp, ip,
-                                  dp, dp, ip, dp, dp, i, ip, i]
+                                  dp, dp, ip, dp, dp, i, ip, i, i, d, d]
         lib.orc_solve.restype = i
         _lib = lib
     return _lib
@@ -155,8 +161,12 @@ def project_compatible(v, lame0):
     return v
 
 
-def fmap(phase, lame_tab, lame0, E, eps):
-    """One application of F: returns (xi, error of eps, <sigma>, max imaginary residue).
+MAPS = {"classical": 0, "polarization": 1}
+
+
+def fmap(phase, lame_tab, lame0, E, eps, map="classical", alpha=2.0, beta=2.0):
+    """One application of F (or of the polarization iteration): returns (xi,
+    error of eps, <sigma>, max imaginary residue).
 
     phase: uint8 (nz, ny, nx); eps: float64 (6, nz, ny, nx)."""
     phase = np.ascontiguousarray(phase, dtype=np.uint8)
@@ -168,8 +178,21 @@ def fmap(phase, lame_tab, lame0, E, eps):
     err = np.zeros(1)
     sav = np.zeros(6)
     im = _load().orc_fmap(nx, ny, nz, _u8(phase), _dp(lt), float(lame0[0]), float(lame0[1]), _dp(E), _dp(eps),
-                          _dp(xi), _dp(err), _dp(sav))
+                          _dp(xi), _dp(err), _dp(sav), MAPS[map], float(alpha), float(beta))
     return xi, float(err[0]), sav, float(im)
+
+
+def polarization_reduced(phase, lame_tab, lame0, E, eps, alpha=2.0):
+    """eps + alpha (C(x) + C0)^{-1} C0 : (F(eps) - eps)."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    nz, ny, nx = phase.shape
+    lt = np.ascontiguousarray(lame_tab, dtype=np.float64)
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    eps = np.ascontiguousarray(eps, dtype=np.float64).reshape(6, nz, ny, nx)
+    out = np.empty_like(eps)
+    _load().orc_polarization_reduced(nx, ny, nz, _u8(phase), _dp(lt), float(lame0[0]), float(lame0[1]), _dp(E),
+                                     _dp(eps), float(alpha), _dp(out))
+    return out
 
 
 class Basis:
@@ -186,8 +209,9 @@ class Basis:
 
 
 def solve(phase, lame_tab, lame0, E, scheme="rpm", tol=1e-8, max_iter=10000, n_max=10, p_max=32, kappa=0.1,
-          replay=None, eps_init=None, basis=None, hist_cap=100000):
-    """Algorithm 1 (scheme='basic') or Algorithm 2 (scheme='rpm') for mean strain E.
+          replay=None, eps_init=None, basis=None, hist_cap=100000, map="classical", alpha=2.0, beta=2.0):
+    """Algorithm 1 (scheme='basic') or Algorithm 2 (scheme='rpm') for mean strain E
+    (map='polarization': the fixed-point operation is Algorithm 3's iteration).
 
     Returns a dict with eps (6, nz, ny, nx), sig_avg, status, iterations (main
     F calls incl. the initial one), jvps, growth, p, residual, history,
@@ -212,7 +236,7 @@ def solve(phase, lame_tab, lame0, E, scheme="rpm", tol=1e-8, max_iter=10000, n_m
                            float(tol), int(max_iter), int(n_max), int(basis.p_max if sch == 1 else 0),
                            float(kappa), _ip(rp), 0 if rp is None else rp.size, _dp(ei), _dp(basis.Z),
                            _dp(basis.W), _dp(basis.H), _ip(p_io), _dp(eps), _dp(sav), _ip(counters), _dp(res),
-                           _dp(hist), hist_cap, _ip(dec), dec.size)
+                           _dp(hist), hist_cap, _ip(dec), dec.size, MAPS[map], float(alpha), float(beta))
     if sch == 1:
         basis.p = int(p_io[0])
     it = int(counters[0])

@@ -24,7 +24,13 @@
  *     inverse FFT, and the equilibrium error of Algorithm 1;
  *   - Algorithm 1 (basic fixed point) and Algorithm 2 (RPM-FFT) including the
  *     basis growth In(q, Z) of Sec. 3 (QR of two successive differences of q,
- *     one or two new columns).
+ *     one or two new columns);
+ *   - the polarization (Accelerated FFT for alpha = beta = 2) iteration of
+ *     Algorithm 3 / Sec. 5.5, with the sign of the reference-medium term of s_b
+ *     taken as s_b = alpha sigma - beta C0:eps (as printed, s_b with +beta
+ *     amplifies every fluctuation by -2 per step even for C = C0; the corrected
+ *     scheme reaches the solution in one step there), and RPM around it
+ *     (Algorithm 2 with F replaced by that iteration, Sec. 5.5).
  *
  * Conventions (readings of the paper, stated once):
  *   - fields are stored as [6][nz][ny][nx] real arrays, x fastest, tensor
@@ -269,7 +275,13 @@ typedef struct {
     const unsigned char *phase;
     const double *lame; /* [n_phases][2] */
     double lam0, mu0;
+    int map;             /* 0: Lippmann-Schwinger map F; 1: polarization iteration */
+    double alpha, beta;  /* polarization parameters (Accelerated FFT: 2, 2) */
 } problem;
+
+static int gauss_solve(int n, const double *A_in, const double *b_in, double *y);
+static void polarization_update(const problem *pr, const double *E6, const double *eps, const double *sig,
+                                double *out);
 
 /* xi = F(eps; E); *err = equilibrium error of eps; sig_avg = <C:eps>.
  * Returns the largest |imaginary part| left by the inverse transform. */
@@ -335,8 +347,16 @@ static double fmap(const problem *pr, const double *E6, const double *eps, doubl
                 for (int c = 0; c < 6; ++c) eh[c * N + x] -= g6[2 * c] + I * g6[2 * c + 1];
             }
 
-    /* xi = F^{-1}[xi_hat] (1/N), real part */
     double max_im = 0.0;
+    if (pr->map == 1) {
+        /* the polarization iteration replaces the update (Algorithm 3) */
+        polarization_update(pr, E6, eps, sig, xi);
+        free(sh);
+        free(eh);
+        free(sig);
+        return 0.0;
+    }
+    /* xi = F^{-1}[xi_hat] (1/N), real part */
     for (int c = 0; c < 6; ++c) {
         fft3(eh + c * N, pr->nx, pr->ny, pr->nz, +1);
         for (long x = 0; x < N; ++x) {
@@ -351,6 +371,79 @@ static double fmap(const problem *pr, const double *E6, const double *eps, doubl
     return max_im;
 }
 
+/* Mandel 6x6 matrix of an isotropic stiffness (shear rows and columns carry
+ * sqrt(2)), from the fourth-order tensor. */
+static const int PAIR_I[6] = {0, 1, 2, 1, 0, 0}, PAIR_J[6] = {0, 1, 2, 2, 2, 1};
+static double mandel_f(int a) { return a < 3 ? 1.0 : sqrt(2.0); }
+static void mandel_stiff(double lam, double mu, double *M)
+{
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 6; ++b)
+            M[a * 6 + b] = mandel_f(a) * mandel_f(b) * stiff(lam, mu, PAIR_I[a], PAIR_J[a], PAIR_I[b], PAIR_J[b]);
+}
+
+/* Algorithm 3, one iteration given eps and sigma = C:eps:
+ *   s_a = sigma + (1 - beta) C0:eps,   s_b = alpha sigma - beta C0:eps,
+ *   eb_hat = -Gamma0(k) : F[s_b] (k != 0),  eb_hat(0) = N beta E,
+ *   eps+ = (C(x) + C0)^{-1} : (s_a + C0 : F^{-1}[eb_hat]),
+ * the inverse taken voxel by voxel on the Mandel matrix. */
+static void polarization_update(const problem *pr, const double *E6, const double *eps, const double *sig,
+                                double *out)
+{
+    long N = pr->N;
+    double *c0e = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+    double *eb = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+    double *sa = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+    cplx *sbh = (cplx *)malloc(sizeof(cplx) * 6 * (size_t)N);
+    unsigned char *zero_ph = (unsigned char *)calloc((size_t)N, 1);
+    double ref[2] = {pr->lam0, pr->mu0};
+    orc_stress(N, zero_ph, ref, eps, c0e); /* C0 : eps */
+    for (int c = 0; c < 6; ++c) {
+        for (long x = 0; x < N; ++x) {
+            sa[c * N + x] = sig[c * N + x] + (1.0 - pr->beta) * c0e[c * N + x];
+            sbh[c * N + x] = pr->alpha * sig[c * N + x] - pr->beta * c0e[c * N + x];
+        }
+        fft3(sbh + c * N, pr->nx, pr->ny, pr->nz, -1);
+    }
+    for (int mz = 0; mz < pr->nz; ++mz)
+        for (int my = 0; my < pr->ny; ++my)
+            for (int mx = 0; mx < pr->nx; ++mx) {
+                long x = ((long)mz * pr->ny + my) * pr->nx + mx;
+                if (x == 0) {
+                    for (int c = 0; c < 6; ++c) sbh[c * N] = (double)N * pr->beta * E6[c];
+                    continue;
+                }
+                double k[3], s6[12], g6[12];
+                orc_wavevector(pr->nx, pr->ny, pr->nz, mx, my, mz, k);
+                for (int c = 0; c < 6; ++c) {
+                    s6[2 * c] = creal(sbh[c * N + x]);
+                    s6[2 * c + 1] = cimag(sbh[c * N + x]);
+                }
+                orc_gamma_apply(k, pr->lam0, pr->mu0, s6, g6);
+                for (int c = 0; c < 6; ++c) sbh[c * N + x] = -(g6[2 * c] + I * g6[2 * c + 1]);
+            }
+    for (int c = 0; c < 6; ++c) {
+        fft3(sbh + c * N, pr->nx, pr->ny, pr->nz, +1);
+        for (long x = 0; x < N; ++x) eb[c * N + x] = creal(sbh[c * N + x]) / (double)N;
+    }
+    orc_stress(N, zero_ph, ref, eb, c0e); /* C0 : eps_b (c0e reused) */
+    double M0[36];
+    mandel_stiff(pr->lam0, pr->mu0, M0);
+    for (long x = 0; x < N; ++x) {
+        double M[36], rhs[6], y[6];
+        mandel_stiff(pr->lame[2 * pr->phase[x]], pr->lame[2 * pr->phase[x] + 1], M);
+        for (int a = 0; a < 36; ++a) M[a] += M0[a];
+        for (int a = 0; a < 6; ++a) rhs[a] = mandel_f(a) * (sa[a * N + x] + c0e[a * N + x]);
+        gauss_solve(6, M, rhs, y);
+        for (int a = 0; a < 6; ++a) out[a * N + x] = y[a] / mandel_f(a);
+    }
+    free(zero_ph);
+    free(sbh);
+    free(sa);
+    free(eb);
+    free(c0e);
+}
+
 static void init_problem(problem *pr, int nx, int ny, int nz, const unsigned char *phase, const double *lame,
                          double lam0, double mu0)
 {
@@ -362,6 +455,9 @@ static void init_problem(problem *pr, int nx, int ny, int nz, const unsigned cha
     pr->lame = lame;
     pr->lam0 = lam0;
     pr->mu0 = mu0;
+    pr->map = 0;
+    pr->alpha = 2.0;
+    pr->beta = 2.0;
 }
 
 /* v <- Gamma0 * (C0 : v) with the k = 0 term removed: the projection onto
@@ -414,13 +510,46 @@ void orc_project_compatible(int nx, int ny, int nz, double lam0, double mu0, dou
     project_compatible(&pr, v);
 }
 
-/* Exported: one application of F.  Returns the max imaginary residue. */
+/* Exported: one application of F (map 0) or of the polarization iteration
+ * (map 1, parameters alpha, beta).  Returns the max imaginary residue (map 0). */
 double orc_fmap(int nx, int ny, int nz, const unsigned char *phase, const double *lame, double lam0, double mu0,
-                const double *E6, const double *eps, double *xi, double *err, double *sig_avg)
+                const double *E6, const double *eps, double *xi, double *err, double *sig_avg, int map,
+                double alpha, double beta)
 {
     problem pr;
     init_problem(&pr, nx, ny, nz, phase, lame, lam0, mu0);
+    pr.map = map;
+    pr.alpha = alpha;
+    pr.beta = beta;
     return fmap(&pr, E6, eps, xi, err, sig_avg);
+}
+
+/* Exported: eps + alpha (C(x) + C0)^{-1} C0 : (F(eps) - eps), the form the
+ * polarization iteration takes on compatible strain fields of mean E (used to
+ * pin the iteration against the Lippmann-Schwinger map). */
+void orc_polarization_reduced(int nx, int ny, int nz, const unsigned char *phase, const double *lame, double lam0,
+                              double mu0, const double *E6, const double *eps, double alpha, double *out)
+{
+    problem pr;
+    init_problem(&pr, nx, ny, nz, phase, lame, lam0, mu0);
+    long N = pr.N;
+    double *xi = (double *)malloc(sizeof(double) * 6 * (size_t)N);
+    double err, sav[6];
+    fmap(&pr, E6, eps, xi, &err, sav);
+    double M0[36];
+    mandel_stiff(lam0, mu0, M0);
+    for (long x = 0; x < N; ++x) {
+        double M[36], rhs[6], y[6];
+        mandel_stiff(lame[2 * phase[x]], lame[2 * phase[x] + 1], M);
+        for (int a = 0; a < 36; ++a) M[a] += M0[a];
+        for (int a = 0; a < 6; ++a) {
+            rhs[a] = 0.0;
+            for (int b = 0; b < 6; ++b) rhs[a] += M0[a * 6 + b] * mandel_f(b) * (xi[b * N + x] - eps[b * N + x]);
+        }
+        gauss_solve(6, M, rhs, y);
+        for (int a = 0; a < 6; ++a) out[a * N + x] = eps[a * N + x] + alpha * y[a] / mandel_f(a);
+    }
+    free(xi);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -524,6 +653,9 @@ static int add_column(long N, double *Z, int p, double *v, double norm0)
  * On return counters = {main-loop F calls (the initial one included), JVP F
  * calls, growth events, basis size} and res_out = {final error, largest
  * imaginary residue left by any inverse transform}.
+ * map 1 replaces F by the polarization iteration of Algorithm 3 with
+ * parameters alpha, beta (Sec. 5.5: RPM-Accelerated FFT for alpha = beta = 2);
+ * its iterates are not compatible, so new basis columns are not projected.
  * Returns 0 converged, 1 not converged in max_iter F calls, 2 diverged
  * (non-finite error or error above 1e6 times the initial one), 3 singular
  * I - H.
@@ -532,10 +664,13 @@ int orc_solve(int nx, int ny, int nz, const unsigned char *phase, const double *
               const double *E6, int scheme, double tol, int max_iter, int n_max, int p_max, double kappa,
               const int *replay, int replay_len, const double *eps_init, double *Z, double *W, double *H, int *p_io,
               double *eps_out, double *sig_avg, int *counters, double *res_out, double *hist, int hist_cap,
-              int *decisions, int dec_cap)
+              int *decisions, int dec_cap, int map, double alpha, double beta)
 {
     problem pr;
     init_problem(&pr, nx, ny, nz, phase, lame, lam0, mu0);
+    pr.map = map;
+    pr.alpha = alpha;
+    pr.beta = beta;
     long N = pr.N, L = 6 * N;
     int p = (scheme == 1) ? *p_io : 0;
     if (scheme == 0) p_max = 0;
@@ -642,8 +777,12 @@ int orc_solve(int nx, int ny, int nz, const unsigned char *phase, const double *
                     want = (have2 && T22 > kappa * T11) ? 2 : 1;
                 }
                 if (replay && growth < replay_len) want = replay[growth];
+                /* the classical map keeps every iterate compatible with mean E, so
+                 * its differences are zero-mean compatible fields and the projection
+                 * only removes rounding residue; the polarization iterates are not
+                 * compatible, and their differences are kept as they are */
                 if (want >= 1 && T11 > 0.0) {
-                    project_compatible(&pr, d1);
+                    if (pr.map == 0) project_compatible(&pr, d1);
                     if (add_column(N, Z, p, d1, 1.0)) {
                         ++p;
                         ++ncol;
@@ -651,7 +790,7 @@ int orc_solve(int nx, int ny, int nz, const unsigned char *phase, const double *
                 }
                 if (want >= 2 && have2 && T22 > 0.0 && p < p_max) {
                     for (long i = 0; i < L; ++i) d2[i] /= T22;
-                    project_compatible(&pr, d2);
+                    if (pr.map == 0) project_compatible(&pr, d2);
                     if (add_column(N, Z, p, d2, 1.0)) {
                         ++p;
                         ++ncol;

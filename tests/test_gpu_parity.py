@@ -40,8 +40,10 @@ def gpu_lame(B, phases):
 
 PHASES3 = [(1.0, 0.3), (7.0, 0.25), (0.2, 0.4)]
 
+# (nz, ny, nx); the 128-point extents take the compile-time transform plans on each axis
 GRIDS = [(1, 32, 32), (1, 6, 8), (1, 48, 12), (4, 6, 8), (2, 4, 6), (8, 8, 8), (12, 16, 6), (9, 3, 6),
-         (3, 9, 27), (16, 16, 16), (6, 96, 4), (32, 12, 48)]
+         (3, 9, 27), (16, 16, 16), (6, 96, 4), (32, 12, 48), (1, 16, 128), (1, 128, 6), (128, 4, 6), (4, 128, 6),
+         (6, 4, 128)]
 
 
 @pytest.mark.parametrize("shape", GRIDS, ids=lambda s: "x".join(map(str, s)))
@@ -115,6 +117,34 @@ def test_rpm_random_3d_fp64(B, shape):
     assert g["iterations"] == ref["iterations"] and g["basis_dim"] == ref["p"]
     eps = g["eps"].cpu().numpy()
     assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
+
+
+def test_warm_start_parity_fp64(B):
+    """A supplied starting field (eps0) against the oracle started from the same field."""
+    w, lt, l0, glt, gl0 = _disk32(B)
+    eps0 = M.random_field(w["phase"].shape, seed=77, scale=0.002) + np.asarray(w["E"])[:, None, None, None]
+    ref = O.solve(w["phase"], lt, l0, w["E"], scheme="rpm", tol=w["tol"], n_max=10, p_max=32, eps_init=eps0)
+    opts = B.make_options(scheme="rpm", tol=w["tol"], n_max=10, p_max=32, replay=list(ref["decisions"]))
+    g = B.fft_solve(dev(w["phase"]), glt, gl0, w["E"], opts, eps0=dev(eps0))
+    assert g["status"] == "RPM_OK" and ref["status"] == "converged"
+    assert g["iterations"] == ref["iterations"] and g["basis_dim"] == ref["p"]
+    eps = g["eps"].cpu().numpy()
+    assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
+    np.testing.assert_allclose(g["history"], ref["history"], rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solution_seeded_start(B, prec):
+    """Started from its own converged field, a solve stops after the first map application."""
+    w, lt, l0, glt, gl0 = _disk32(B)
+    tol = 1e-8 if prec == "fp64" else 1e-5
+    opts = B.make_options(scheme="rpm", tol=tol, precision=prec, refine=0)
+    g = B.fft_solve(dev(w["phase"]), glt, gl0, w["E"], opts)
+    assert g["status"] == "RPM_OK" and g["iterations"] > 1
+    g2 = B.fft_solve(dev(w["phase"]), glt, gl0, w["E"], opts, eps0=g["eps"])
+    assert g2["status"] == "RPM_OK" and g2["iterations"] == 1
+    assert g2["residual"] <= tol
+    assert (g2["eps"] == g["eps"]).all()
 
 
 def test_effective_tensor_2d_fp64(B):

@@ -412,3 +412,76 @@ def test_compatible_projection():
     # the result lies in the span of the explicit compatible basis
     pm = (pg.reshape(6, -1) * CF.MANDEL_W[:, None]).ravel()
     np.testing.assert_allclose(V @ (V.T @ pm), pm, atol=1e-12)
+
+
+# ------------------------------------------------ polarization iteration (Sec. 5.5, Algorithm 3)
+
+def test_polarization_homogeneous_one_step():
+    """C = C0, alpha = beta = 2: one iteration from any field returns the uniform mean strain."""
+    ph = np.zeros((4, 6, 8), np.uint8)
+    lt = O.lame_table([(3.0, 0.3)])
+    E = np.array([0.01, -0.002, 0.003, 0.001, 0.002, -0.001])
+    eps = M.random_field(ph.shape, seed=3, scale=0.01)
+    xi, _, _, _ = O.fmap(ph, lt, O.lame(3.0, 0.3), E, eps, map="polarization")
+    np.testing.assert_allclose(xi, np.broadcast_to(E[:, None, None, None], xi.shape), rtol=0, atol=1e-17)
+
+
+def test_polarization_reduced_form_on_compatible_fields():
+    """On compatible fields of mean E the iteration equals eps + alpha (C + C0)^-1 C0 (F(eps) - eps);
+    on other fields it does not (its beta terms act on the incompatible part)."""
+    ph = M.random_phases((6, 8, 10), 3, seed=5)
+    lt = O.lame_table([(1.0, 0.3), (7.0, 0.25), (0.2, 0.4)])
+    l0 = O.lame(3.0, 0.3)
+    E = np.array([0.01, -0.002, 0.003, 0.001, 0.002, -0.001])
+    v = O.project_compatible(M.random_field(ph.shape, seed=9, scale=0.01), l0) + E[:, None, None, None]
+    for alpha in (2.0, 1.5):
+        a, _, _, _ = O.fmap(ph, lt, l0, E, v, map="polarization", alpha=alpha, beta=alpha)
+        b = O.polarization_reduced(ph, lt, l0, E, v, alpha=alpha)
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
+    w = M.random_field(ph.shape, seed=10, scale=0.01)
+    a, _, _, _ = O.fmap(ph, lt, l0, E, w, map="polarization")
+    b = O.polarization_reduced(ph, lt, l0, E, w)
+    assert np.abs(a - b).max() > 1e-3 * np.abs(a).max()
+
+
+def test_polarization_fixed_point_is_the_solution():
+    """The exact discrete solution is a fixed point of the iteration; its error vanishes."""
+    shape = (4, 4, 4)
+    ph = M.random_phases(shape, 2, seed=6)
+    lt = np.array([CF.lame(*p) for p in [(1.0, 0.3), (5.0, 0.2)]])
+    E = np.array([0.01, -0.002, 0.003, 0.001, 0.0, 0.004])
+    eps, _ = CF.galerkin_solution(ph, lt, E)
+    xi, err, _, _ = O.fmap(ph, lt, CF.lame(2.2, 0.3), E, eps, map="polarization")
+    assert err < 1e-12
+    np.testing.assert_allclose(xi, eps, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme", ["basic", "rpm"])
+def test_polarization_reaches_the_direct_solution(scheme):
+    """Algorithm 3 (and RPM around it) converges to the Galerkin solution, including a
+    contrast where the Lippmann-Schwinger map with the same reference medium diverges."""
+    shape = (4, 6, 6)
+    ph = M.random_phases(shape, 3, seed=13)
+    tab = [(1.0, 0.3), (40.0, 0.25), (0.5, 0.4)]
+    lt = np.array([CF.lame(*p) for p in tab])
+    E = np.array([0.01, -0.004, 0.002, 0.003, -0.002, 0.005])
+    ref_eps, ref_sig = CF.galerkin_solution(ph, lt, E)
+    l0 = CF.lame(np.sqrt(0.5 * 40.0), 0.3)  # geometric mean of the extreme moduli
+    cl = O.solve(ph, lt, l0, E, scheme="basic", tol=1e-12, max_iter=400)
+    assert cl["status"] == "diverged"
+    r = O.solve(ph, lt, l0, E, scheme=scheme, tol=1e-12, max_iter=20000, n_max=5, map="polarization")
+    assert r["status"] == "converged", (r["status"], r["residual"])
+    np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
+    np.testing.assert_allclose(r["sig_avg"], ref_sig, atol=1e-12)
+
+
+def test_polarization_laminate_exact():
+    ph = M.laminate((4, 4, 8), [0, 0, 1, 1, 1, 0, 2, 0], axis=2)
+    lt = np.array([CF.lame(*p) for p in [(1.0, 0.3), (8.0, 0.25), (3.0, 0.35)]])
+    E = np.array([0.01, 0.002, -0.003, 0.004, -0.001, 0.002])
+    ref_eps, ref_sig = CF.laminate_solution(ph, lt, E, 2)
+    r = O.solve(ph, lt, CF.lame(np.sqrt(8.0), 0.3), E, scheme="rpm", tol=1e-13, max_iter=5000,
+                map="polarization")
+    assert r["status"] == "converged"
+    np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
+    np.testing.assert_allclose(r["sig_avg"], ref_sig, atol=1e-12)
