@@ -24,6 +24,86 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the kernel classes, measured with hardware counters
+# (rocprofv3 FETCH_SIZE / WRITE_SIZE) and written by --traffic-from; it is only
+# reported while the kernel sources are the ones it was measured on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_128cube_voids_fp32.json")
+KERNEL_SOURCES = ["include/rpmfft.h", "paper_2003_07720_amd/csrc/rpm_device.h",
+                  "paper_2003_07720_amd/csrc/rpm_kernels.h", "paper_2003_07720_amd/csrc/rpm_solver.hip"]
+# kernel symbols (FP32 path) behind each timing class of rpm_stats
+CLASS_SYMBOLS = {
+    "xfwd": r"rpm::k_xfwd<float, (true|false)>",
+    "yfwd": r"rpm::k_ypipe<float, -1, \d+>|rpm::k_yfwd<float>",
+    "gamma": r"rpm::k_gamma<float>",
+    "yinv": r"rpm::k_ypipe<float, 1, \d+>|rpm::k_yinv<float>",
+    "xinv": r"rpm::k_xinv<float>",
+    "project": r"rpm::k_gdots<float, float, [12], 0>",
+    "recombine": r"rpm::k_recombine<float>",
+}
+
+
+def source_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from(fetch_csv, write_csv, copy_mib, steps, seed, out_path):
+    """Per-launch HBM bytes of each kernel class from two rocprofv3 --pmc runs of
+    this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
+    what the same counter reads for the plain copy of copy_mib MiB that
+    --calibrate-copy-mib appends to the run."""
+    import csv
+    import re
+
+    def load(path, counter):
+        rows = []
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+        return rows
+
+    copy_bytes = copy_mib * float(1 << 20)
+    out = {"workload": "128^3 voids FP32 (bench.py defaults)", "steps": steps, "seed": seed, "copy_mib": copy_mib,
+           "source_sha256": source_digest(), "classes": {}}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = load(path, counter)
+        # the calibration copies are the three largest copy dispatches
+        copies = sorted(v for k, v in rows if "copyBuffer" in k)[-3:]
+        scale = copy_bytes / (sum(copies) / len(copies))
+        out[counter.lower() + "_scale"] = scale
+        for cls, pat in CLASS_SYMBOLS.items():
+            vals = [v for k, v in rows if re.search(pat, k.split("(")[0])]
+            if not vals:
+                continue
+            c = out["classes"].setdefault(cls, {"dispatches": len(vals)})
+            c[counter.lower() + "_bytes_per_launch"] = scale * sum(vals) / len(vals)
+    for c in out["classes"].values():
+        c["traffic_bytes_per_launch"] = c.get("fetch_size_bytes_per_launch", 0.0) + c.get(
+            "write_size_bytes_per_launch", 0.0)
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def measured_traffic(cls, steps, seed):
+    """Counter-measured bytes per launch of a class, or None when absent or
+    measured on other sources or another step count."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != source_digest() or t.get("steps") != steps or t.get("seed") != seed:
+        return None
+    c = t.get("classes", {}).get(cls)
+    return None if c is None else c.get("traffic_bytes_per_launch")
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -43,11 +123,68 @@ def parse():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a float32 buffer of this many MiB three times (a plain copy kernel "
                          "of known size that scales hardware byte counters)")
+    ap.add_argument("--table1", action="store_true",
+                    help="instead of the benchmark: the contrast sweep of Sec. 5.5 (128^2 fibre, polarization "
+                         "iteration alone and with RPM, FP64, tol 1e-4); prints its own JSON line")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --warmup 0 --no-cpu --no-ttt --calibrate-copy-mib M' into per-launch traffic "
+                         "(written to profiles/)")
     return ap.parse_args()
+
+
+# Iterations and seconds printed in Table 1 (Sec. 5.5; Matlab, hardware not
+# stated): K -> (Acc-FFT, RPM-Acc-FFT iterations, Acc-FFT s, RPM-Acc-FFT s).
+TABLE1 = {500: (234, 83, 6.46, 4.47), 1000: (335, 81, 8.51, 4.42), 5000: (335, 81, 20.24, 4.40),
+          10000: (1136, 82, 28.29, 4.44), 50000: (2741, 82, 68.56, 4.45), 100000: (3863, 161, 98.60, 11.13)}
+
+
+def table1():
+    """The contrast sweep of Table 1 on this implementation: the polarization
+    iteration with alpha = beta = 2 (Accelerated FFT) alone and with RPM."""
+    import torch
+
+    from paper_2003_07720_amd import binding as B
+    from paper_2003_07720_amd import microstructure as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rows = []
+    for K, paper in TABLE1.items():
+        w = M.workload_fibre(K)
+        phase = torch.from_numpy(w["phase"]).to("cuda")
+        lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
+        l0 = B.lame_from_young(*w["ref"])
+        row = dict(K=K, paper=dict(zip(("acc_iters", "rpm_acc_iters", "acc_s", "rpm_acc_s"), paper)))
+        for scheme in ("basic", "rpm"):
+            opts = B.make_options(scheme=scheme, map="polarization", tol=w["tol"], max_iter=20000, n_max=10,
+                                  p_max=32)
+            ws = B.make_workspace(tuple(phase.shape), opts)
+            B.fft_solve(phase, lt, l0, w["E"], B.make_options(scheme=scheme, map="polarization", max_iter=3),
+                        workspace=ws, want_eps=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = B.fft_solve(phase, lt, l0, w["E"], opts, workspace=ws, want_eps=False)
+            torch.cuda.synchronize()
+            row[scheme] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"], p=r["basis_dim"],
+                               residual=r["residual"], seconds=round(time.perf_counter() - t0, 4))
+        rows.append(row)
+        print(f"table1: K={K} {row}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "iterations and seconds to 1e-4, 128^2 fibre, Accelerated FFT vs RPM-Accelerated FFT",
+                      "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": "128^2 centred fibre radius 32, nu 0.25, eps_12 0.5%, "
+                                             "E0 = sqrt(K), alpha = beta = 2, n_max 10, p_max 32"},
+                      "rows": rows}), flush=True)
 
 
 def main():
     a = parse()
+    if a.traffic_from:
+        traffic_from(a.traffic_from[0], a.traffic_from[1], a.calibrate_copy_mib or 1024, a.steps, a.seed,
+                     TRAFFIC_FILE)
+        return
+    if a.table1 and a.gpus == 1:
+        table1()
+        return
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} refused: this build runs on a single GPU (one process, one device); "
               f"run with --gpus 1", file=sys.stderr)
@@ -98,6 +235,7 @@ def main():
     avg_ms = kms[dom] / launches
     bytes_per_launch = r["kernel_bytes"][dom] / launches
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, a.steps, a.seed) if a.precision == "fp32" and a.n == 128 else None
     per_kernel = {k: dict(ms_total=round(kms[k], 4), launches=r["kernel_launches"][k],
                           avg_us=round(1e3 * kms[k] / max(r["kernel_launches"][k], 1), 3),
                           gbs=round(r["kernel_bytes"][k] / max(kms[k], 1e-12) / 1e6, 1))
@@ -149,7 +287,7 @@ def main():
                           f"RPM) on the same {a.n}^3 void cell, {c1 - c0:.1f} s")
 
     out = {
-        "metric": "voxel-iters/s + time to 1e-6 residual at 128^3 voids; warm-start vs plain RPM",
+        "metric": "voxel-iters/s + time to 1e-6 residual at 128\u00b3 voids; warm-start vs plain RPM",
         "value": value,
         "unit": "voxel-iters/s",
         "n_gpus": 1,
@@ -167,7 +305,7 @@ def main():
                    "voxels": N, "p_end": r["basis_dim"], "jvps": r["jvps"],
                    "time_to_tol_s": ttt, "time_to_tol_run": ttt_info},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "avg_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per_launch},
         "kernels": per_kernel,
         "cpu_baseline": cpu,

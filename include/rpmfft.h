@@ -72,6 +72,12 @@ typedef enum {
 enum { RPM_SCHEME_BASIC = 0, /* Algorithm 1: eps <- F(eps)                       */
        RPM_SCHEME_RPM = 1 }; /* Algorithm 2                                      */
 
+enum { RPM_MAP_LS = 0,             /* the Lippmann-Schwinger map F (Algorithm 1)  */
+       RPM_MAP_POLARIZATION = 1 };  /* the polarization iteration of Algorithm 3
+                                       (Sec. 5.5; Accelerated FFT for
+                                       alpha = beta = 2) with the C0 term of s_b
+                                       taken as -beta C0:eps                      */
+
 enum { RPM_FP64 = 0,         /* fields, FFTs and Z in double                     */
        RPM_FP32 = 1 };       /* fields, FFTs and Z in float; reductions, norms,
                                 Gram-Schmidt coefficients, H and the Newton
@@ -118,6 +124,10 @@ typedef struct {
                                  the status then reflects the FP64 error       */
     double refine_tol;        /* correction solves stop at |G(d) - d| <=
                                  refine_tol |g| (0 < refine_tol < 1)           */
+    int32_t map;              /* RPM_MAP_LS or RPM_MAP_POLARIZATION: the fixed-
+                                 point operation of both schemes (Sec. 5.5: RPM
+                                 around the polarization iteration)              */
+    double alpha, beta;       /* polarization parameters (> 0; default 2, 2)     */
 } rpm_options;
 
 typedef struct {
@@ -144,7 +154,7 @@ typedef struct {
 
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
  * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
- * refine 4, refine_tol 1e-3. */
+ * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2. */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and
@@ -152,7 +162,12 @@ void rpm_default_options(rpm_options *o);
  * non-finite input. */
 rpm_status rpm_lame_from_young(double E, double nu, double *lam, double *mu);
 
-/* Bytes of device workspace needed for grid n under options o. */
+/* Bytes of device workspace needed for grid n under options o.
+ * RPM_E_UNSUPPORTED_SIZE when an extent is not 2,3-smooth in [2, 512] (nz may
+ * be 1), or when a pencil pass would not fit its LDS tile: with the
+ * polarization map the z (2-D: y) pencils carry 12 components, which bounds
+ * their length to 144 in FP64 and, since FP32 fields are certified in FP64,
+ * in FP32 as well. */
 rpm_status rpm_workspace_size(const int32_t n[3], const rpm_options *o, size_t *bytes);
 
 /*

@@ -27,6 +27,7 @@ KERNEL_NAMES = ["xfwd", "yfwd", "gamma", "yinv", "xinv", "reduce", "finalize", "
 STATUS = {0: "RPM_OK", 1: "RPM_NOT_CONVERGED", 2: "RPM_DIVERGED", 3: "RPM_SINGULAR", -1: "RPM_E_INVALID",
           -2: "RPM_E_UNSUPPORTED_SIZE", -3: "RPM_E_WORKSPACE", -5: "RPM_E_HIP"}
 SCHEME = {"basic": 0, "rpm": 1}
+MAP = {"classical": 0, "polarization": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
 
 
@@ -40,7 +41,8 @@ class RpmOptions(ctypes.Structure):
                 ("p_max", ctypes.c_int32), ("kappa", ctypes.c_double), ("scheme", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("reuse_basis", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("replay", ctypes.POINTER(ctypes.c_int32)), ("replay_len", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double)]
+                ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class RpmStats(ctypes.Structure):
@@ -104,6 +106,8 @@ def make_options(**kw):
             v = SCHEME[v]
         if k == "precision" and isinstance(v, str):
             v = PRECISION[v]
+        if k == "map" and isinstance(v, str):
+            v = MAP[v]
         setattr(o, k, v)
     keep = None
     if replay is not None and len(replay) > 0:

@@ -32,6 +32,7 @@ struct Geo {
     int tz;                // z columns per y-pass tile
     int np;                // pencils per gamma tile
     int two_d;
+    int ncomp;             // spectral components of the forward passes (6, or 12 with eps)
     FDiv fnx, fny, fnh, fty, ftz, frow;  // divisions by nx, ny, nh, ty, tz and the gamma row length
 };
 
@@ -98,14 +99,15 @@ template <>
 struct MaxV<double> { static constexpr int v = 4; };
 
 // ---------------------------------------------------------------------------
-// x-forward: recombination + constitutive law + R2C FFT along x.
+// x-forward: constitutive law + R2C FFT along x (two real components per
+// complex transform), per-block <eps> partial sums.  POL: eps is transformed
+// too (components 6..11 of S1), for the polarization iteration.
 // grid: nz * (ny / ty) blocks.  LDS: 2 * ty * lrow(nx) + nx complex + reduction.
 // ---------------------------------------------------------------------------
-template <typename T, bool VEC>
-__global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const T* __restrict__ Z, int p, int zP,
-                                                   const double* __restrict__ dco, T* __restrict__ eps_out,
-                                                   const uint8_t* __restrict__ phase, const double* __restrict__ lame,
-                                                   int use_ref, double lam0, double mu0, cx<T>* __restrict__ S1,
+template <typename T, bool VEC, bool POL>
+__global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const uint8_t* __restrict__ phase,
+                                                   const double* __restrict__ lame, int use_ref, double lam0,
+                                                   double mu0, cx<T>* __restrict__ S1,
                                                    double* __restrict__ part_mean, Geo g, Plan px,
                                                    const cx<T>* __restrict__ twx, const int* __restrict__ done)
 {
@@ -131,6 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
     constexpr int VL = VEC ? (int)(16 / sizeof(T)) : 1;
     using V = typename Vec4<T>::type;
     T sig[MV][6];
+    T ev[POL ? MV : 1][6];
     double msum[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
     for (int i = 0; i < MV / VL; ++i) {
@@ -149,35 +152,6 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
                     e[0][c] = xin[c * N + gi];
                 }
             }
-            for (int j = 0; j < p; ++j) {
-                const T dj = (T)dco[j];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const T* zj = Z + zix(c * N + gi, j, zP);
-                    if constexpr (VEC) {
-                        const V t = *reinterpret_cast<const V*>(zj);
-                        const T* ts = reinterpret_cast<const T*>(&t);
-#pragma unroll
-                        for (int u = 0; u < VL; ++u) e[u][c] += dj * ts[u];
-                    } else {
-                        e[0][c] += dj * zj[0];
-                    }
-                }
-            }
-            if (eps_out) {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    if constexpr (VEC) {
-                        V t;
-                        T* ts = reinterpret_cast<T*>(&t);
-#pragma unroll
-                        for (int u = 0; u < VL; ++u) ts[u] = e[u][c];
-                        *reinterpret_cast<V*>(eps_out + c * N + gi) = t;
-                    } else {
-                        eps_out[c * N + gi] = e[0][c];
-                    }
-                }
-            }
 #pragma unroll
             for (int u = 0; u < VL; ++u) {
 #pragma unroll
@@ -194,19 +168,26 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
                 const T ltr = lam * (e[u][0] + e[u][1] + e[u][2]);
                 const T m2 = mu + mu;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sig[i * VL + u][c] = m2 * e[u][c] + (c < 3 ? ltr : T(0));
+                for (int c = 0; c < 6; ++c) {
+                    sig[i * VL + u][c] = m2 * e[u][c] + (c < 3 ? ltr : T(0));
+                    if constexpr (POL) ev[i * VL + u][c] = e[u][c];
+                }
             }
         } else {
 #pragma unroll
             for (int u = 0; u < VL; ++u)
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sig[i * VL + u][c] = T(0);
+                for (int c = 0; c < 6; ++c) {
+                    sig[i * VL + u][c] = T(0);
+                    if constexpr (POL) ev[i * VL + u][c] = T(0);
+                }
         }
     }
     if (part_mean) wg_sum_store<6>(msum, part_mean + (long long)blockIdx.x * 6, red);
 
     const int nh = g.nh;
-    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int q = 0; q < (POL ? 6 : 3); ++q) {  // unrolled: the register arrays take constant indices
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < MV / VL; ++i) {
@@ -215,7 +196,16 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
                 const int r = g.fnx.div(v0);
                 const int x = v0 - r * nx;
 #pragma unroll
-                for (int u = 0; u < VL; ++u) A[r * ss + lpad(x + u)] = cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]};
+                for (int u = 0; u < VL; ++u) {
+                    cx<T> val;
+                    if constexpr (POL) {
+                        val = q < 3 ? cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]}
+                                    : cx<T>{ev[i * VL + u][2 * q - 6], ev[i * VL + u][2 * q - 5]};
+                    } else {
+                        val = cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]};
+                    }
+                    A[r * ss + lpad(x + u)] = val;
+                }
             }
         }
         __syncthreads();
@@ -426,19 +416,25 @@ __device__ __forceinline__ void wave_vector(int kx, int ky, int kz, const Geo& g
 // s = sigma_hat n, c0 = (lam0 + mu0)/(mu0 (lam0 + 2 mu0))), the equilibrium
 // error sum_m |k . sigma_hat|^2 = |k|^2 |s|^2 (half-spectrum weights), the
 // k = 0 term, and the inverse FFT, in place.
+// POL (polarization iteration, Algorithm 3): the pencils also carry eps_hat
+// (components 6..11); the Green operator acts on s_b = alpha sigma_hat -
+// beta C0:eps_hat, the k = 0 entry is -N beta E, and only the six components
+// of the result go back (the error still measures sigma_hat).
 // 3-D: rows along z of S2 (pencil = ky * nh + kx).  2-D: rows along y of S1
 // (pencil = kx, kz = 0).  grid: ceil(npencils / np).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool POL>
 __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g, Plan pr,
                                                     const cx<T>* __restrict__ twr, double lam0, double mu0,
-                                                    int dc_mode, const double* __restrict__ E,
+                                                    double alpha, double beta, int dc_mode,
+                                                    const double* __restrict__ E,
                                                     const double* __restrict__ part_mean, int n_mean,
                                                     double* __restrict__ part_err, DevState* __restrict__ st,
                                                     const int* __restrict__ done)
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NC = POL ? 12 : 6;
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
     const int ss = lrow(nrow);
@@ -446,12 +442,12 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
     const int npl = min(g.np, npen - p0);
     const int nseq = 6 * npl;
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
-    cx<T>* B = A + 6 * g.np * ss;
-    cx<T>* tw = B + 6 * g.np * ss;
+    cx<T>* B = A + NC * g.np * ss;
+    cx<T>* tw = B + NC * g.np * ss;
     double* red = reinterpret_cast<double*>(tw + nrow);
 
     for (int i = threadIdx.x; i < nrow; i += kThreads) tw[i] = twr[i];
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < NC; ++c) {
         const cx<T>* src = S + (long long)c * g.nspec + (long long)p0 * nrow;
         for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
             const int pl = g.frow.div(t);
@@ -472,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
         wg_sum_store<6>(acc, dc_mean, red);
     }
     __syncthreads();
-    cx<T>* R = lds_fft<T, -1>(A, B, pr, nseq, ss, tw);
+    cx<T>* R = lds_fft<T, -1>(A, B, pr, NC * npl, ss, tw);
 
     const double c0 = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
     const double imu = 1.0 / mu0;
@@ -494,6 +490,24 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
         cx<T> s[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) s[c] = R[(c * npl + pl) * ss + lpad(i)];
+        // the field the Green operator acts on: sigma_hat, or s_b (POL)
+        cx<T> sg[6];
+        if constexpr (POL) {
+            cx<T> e[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) e[c] = R[((6 + c) * npl + pl) * ss + lpad(i)];
+            const cx<T> tr = cadd(cadd(e[0], e[1]), e[2]);
+            const T al = (T)alpha, bl = (T)(beta * lam0), b2m = (T)(2.0 * beta * mu0);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                cx<T> v = csub(cscale(s[c], al), cscale(e[c], b2m));
+                if (c < 3) v = csub(v, cscale(tr, bl));
+                sg[c] = v;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sg[c] = s[c];
+        }
         cx<T> o[6];
         if (kx == 0 && ky == 0 && kz == 0) {
             const double Nd = (double)g.N;
@@ -501,7 +515,9 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
             for (int c = 0; c < 6; ++c) {
                 st->sig_hat0[c] = (double)s[c].x;
                 st->mean_eps[c] = dc_mean[c] / Nd;
-                const double v = (dc_mode == DC_MEAN) ? (dc_mean[c] - Nd * E[c]) : 0.0;
+                double v;
+                if constexpr (POL) v = (dc_mode == DC_MEAN) ? -Nd * beta * E[c] : 0.0;
+                else v = (dc_mode == DC_MEAN) ? (dc_mean[c] - Nd * E[c]) : 0.0;
                 o[c] = cx<T>{(T)v, T(0)};
             }
         } else {
@@ -511,13 +527,18 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
             const double ik = 1.0 / sqrt(kk);
             const T n0 = (T)(k[0] * ik), n1 = (T)(k[1] * ik), n2 = (T)(k[2] * ik);
             // s = sigma_hat n with components xx,yy,zz,yz,xz,xy = 0..5
-            const cx<T> sx = cadd(cadd(cscale(s[0], n0), cscale(s[5], n1)), cscale(s[4], n2));
-            const cx<T> sy = cadd(cadd(cscale(s[5], n0), cscale(s[1], n1)), cscale(s[3], n2));
-            const cx<T> sz = cadd(cadd(cscale(s[4], n0), cscale(s[3], n1)), cscale(s[2], n2));
+            cx<T> sx = cadd(cadd(cscale(s[0], n0), cscale(s[5], n1)), cscale(s[4], n2));
+            cx<T> sy = cadd(cadd(cscale(s[5], n0), cscale(s[1], n1)), cscale(s[3], n2));
+            cx<T> sz = cadd(cadd(cscale(s[4], n0), cscale(s[3], n1)), cscale(s[2], n2));
             const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
             esum += w * kk *
                     ((double)sx.x * sx.x + (double)sx.y * sx.y + (double)sy.x * sy.x + (double)sy.y * sy.y +
                      (double)sz.x * sz.x + (double)sz.y * sz.y);
+            if constexpr (POL) {
+                sx = cadd(cadd(cscale(sg[0], n0), cscale(sg[5], n1)), cscale(sg[4], n2));
+                sy = cadd(cadd(cscale(sg[5], n0), cscale(sg[1], n1)), cscale(sg[3], n2));
+                sz = cadd(cadd(cscale(sg[4], n0), cscale(sg[3], n1)), cscale(sg[2], n2));
+            }
             const cx<T> a = cadd(cadd(cscale(sx, n0), cscale(sy, n1)), cscale(sz, n2));
             const T m1 = (T)imu, cc = (T)c0, hm = T(0.5) * (T)imu;
             o[0] = csub(cscale(sx, m1 * n0), cscale(a, cc * n0 * n0));
@@ -546,13 +567,19 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
 
 // ---------------------------------------------------------------------------
 // x-inverse: complex-to-real FFT along x, out = eps - t (OUT_XI) or t (OUT_T).
+// POL (polarization iteration, Algorithm 3, OUT_XI only): t is Gamma0 s_b -
+// beta E, eps_b = -t, and out = (C(x) + C0)^{-1} (sigma + (1 - beta) C0 eps +
+// C0 eps_b) with sigma = C(x) eps, voxel by voxel once all six components of t
+// are back.
 // grid: nz * (ny / ty).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool POL>
 __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
                                                    T* __restrict__ out, int out_mode, const T* __restrict__ shift,
                                                    double* __restrict__ part_inc, Geo g, Plan px,
-                                                   const cx<T>* __restrict__ twx, const int* __restrict__ done)
+                                                   const cx<T>* __restrict__ twx, const uint8_t* __restrict__ phase,
+                                                   const double* __restrict__ lame, double lam0, double mu0,
+                                                   double beta, const int* __restrict__ done)
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -571,6 +598,8 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
 
     for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
     double inc = 0.0;  // sum of w (out - eps)^2 over the tile (correction solves)
+    T tb[POL ? MV : 1][6];  // POL: t of this thread's voxels, all components
+#pragma unroll
     for (int q = 0; q < 3; ++q) {
         __syncthreads();
         const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
@@ -600,10 +629,13 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                 const int x = v - r * nx;
                 const cx<T> val = R[r * ss + lpad(x)];
                 const long long gi = base + v;
-                const T ta = val.x * invN, tb = val.y * invN;
-                if (out_mode == OUT_XI) {
+                const T ta = val.x * invN, tb_ = val.y * invN;
+                if constexpr (POL) {
+                    tb[i][2 * q] = ta;
+                    tb[i][2 * q + 1] = tb_;
+                } else if (out_mode == OUT_XI) {
                     const T ea = eps[ca * N + gi], eb = eps[cb * N + gi];
-                    T oa = ea - ta, ob = eb - tb;
+                    T oa = ea - ta, ob = eb - tb_;
                     if (shift) {
                         oa += shift[ca * N + gi];
                         ob += shift[cb * N + gi];
@@ -616,7 +648,46 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                     }
                 } else {
                     out[ca * N + gi] = ta;
-                    out[cb * N + gi] = tb;
+                    out[cb * N + gi] = tb_;
+                }
+            }
+        }
+    }
+    if constexpr (POL) {
+        const T l0 = (T)lam0, m0 = (T)mu0, omb = (T)(1.0 - beta);
+#pragma unroll
+        for (int i = 0; i < MV; ++i) {
+            const int v = threadIdx.x + i * kThreads;
+            if (v < nvox) {
+                const long long gi = base + v;
+                T e[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) e[c] = eps[c * N + gi];
+                const int ph = phase[gi];
+                const T lam = (T)lame[2 * ph], mu = (T)lame[2 * ph + 1];
+                const T tre = e[0] + e[1] + e[2];
+                const T tru = tb[i][0] + tb[i][1] + tb[i][2];
+                // X = sigma + (1 - beta) C0 eps - C0 t
+                T X[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    X[c] = T(2) * (mu + omb * m0) * e[c] - T(2) * m0 * tb[i][c];
+                    if (c < 3) X[c] += (lam + omb * l0) * tre - l0 * tru;
+                }
+                // (C + C0)^{-1} X for the isotropic sum (lam + lam0, mu + mu0)
+                const T lp = lam + l0, mp = mu + m0;
+                const T trX = X[0] + X[1] + X[2];
+                const T kap = lp / (T(3) * lp + T(2) * mp);
+                const T inv2m = T(1) / (T(2) * mp);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    T o = (c < 3 ? X[c] - kap * trX : X[c]) * inv2m;
+                    if (shift) o += shift[c * N + gi];
+                    out[c * N + gi] = o;
+                    if (part_inc) {
+                        const double dd = (double)o - (double)e[c];
+                        inc += frob_w(c) * dd * dd;
+                    }
                 }
             }
         }
@@ -730,7 +801,9 @@ __device__ __forceinline__ void gdots_tile(const TA* __restrict__ a0t, const TA*
     }
 }
 
-template <typename TA, typename TZ, int NF>
+// SITE only separates the call sites in profiles (0: the per-step
+// projections, 1: basis growth); the code is the same.
+template <typename TA, typename TZ, int NF, int SITE>
 __global__ __launch_bounds__(512) void k_gdots(const TA* __restrict__ a0, const TA* __restrict__ a1,
                                                const TZ* __restrict__ Z, int p, int zP, long long N,
                                                double* __restrict__ part, int ld)
@@ -922,10 +995,27 @@ __global__ __launch_bounds__(kThreads) void k_tdots(TA* __restrict__ a0, const T
 
 // ---------------------------------------------------------------------------
 // Reductions of per-block partial sums (fixed order: deterministic).
-// out[0] = sum of part_err; out[1 + o] for o < nf * p = column map(o) of
-// part_dots (zeta_j at column j, z_j at column ld + j; column-major, G_dots
-// partials per column).
-// grid: 1 + nf * p.
+// ---------------------------------------------------------------------------
+// out[j] = sum_b part[b * bs + j * cs], j < m.  grid: m.
+__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restrict__ part, int G, long long bs,
+                                                          long long cs, double* __restrict__ out)
+{
+    __shared__ double red[kWaves];
+    __shared__ double tot[1];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < G; b += kThreads) acc += part[(long long)b * bs + j * cs];
+    double v[1] = {acc};
+    wg_sum_store<1>(v, tot, red);
+    if (threadIdx.x == 0) out[j] = tot[0];
+}
+
+// ---------------------------------------------------------------------------
+// Reductions at the end of a step, one block per output: out[0] = sum of the
+// error partials (part_err, G_err entries); out[1 + q] for q < nf * p = sum of
+// partial column map(q) of the basis products (column-major part_dots, G_dots
+// per column: zeta_j at column j and, nf = 2, z_j at column ld + j).  Fixed
+// order: deterministic.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kThreads) void k_reduce_main(const double* __restrict__ part_err, int G_err,
                                                           const double* __restrict__ part_dots, int G_dots, int ld,
@@ -942,50 +1032,50 @@ __global__ __launch_bounds__(kThreads) void k_reduce_main(const double* __restri
             for (int b = threadIdx.x; b < G_err; b += kThreads) acc += part_err[b];
     } else {
         const int q = o - 1;
-        const int col = q < p ? q : ld + (q - p);
-        for (int b = threadIdx.x; b < G_dots; b += kThreads) acc += part_dots[(long long)col * G_dots + b];
+        const double* src = part_dots + (long long)(q < p ? q : ld + (q - p)) * G_dots;
+        for (int b = threadIdx.x; b < G_dots; b += kThreads) acc += src[b];
     }
     double v[1] = {acc};
     wg_sum_store<1>(v, tot, red);
     if (threadIdx.x == 0) out[o] = tot[0];
 }
 
-// out[j] = sum_b part[b * bs + j * cs], j < m.  grid: m.
-__global__ __launch_bounds__(kThreads) void k_reduce_cols(const double* __restrict__ part, int G, long long bs,
-                                                          long long cs, double* __restrict__ out)
-{
-    __shared__ double red[kWaves];
-    __shared__ double tot[1];
-    const int j = blockIdx.x;
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < G; b += kThreads) acc += part[(long long)b * bs + j * cs];
-    double v[1] = {acc};
-    wg_sum_store<1>(v, tot, red);
-    if (threadIdx.x == 0) out[j] = tot[0];
-}
-
 // ---------------------------------------------------------------------------
-// finalize (one wave): equilibrium error of the iterate that went through F,
-// convergence / divergence / budget tests, and the Newton step on the
-// unstable subspace z' = z + (I - H)^{-1}(zeta - z), applied as a product with
-// the inverse kept by k_factor, giving the recombination coefficients
-// d = z' - zeta for the next iterate eps_next = xi + Z d.
+// End of a step (one block of kThreads) on the reduced sums: the equilibrium
+// error of the iterate that went through F, the convergence / divergence /
+// budget tests, and the Newton step on the unstable subspace
+// z' = z + (I - H)^{-1}(zeta - z), applied as a product with the inverse kept
+// by k_factor, giving the recombination coefficients d = z' - zeta for the
+// next iterate eps_next = xi + Z d.
 // direct: z = Z^T eps was reduced into sums (after a basis change or at the
 // start of a solve); otherwise eps = xi_prev + Z d_prev was built from the
 // stored pair, so z = zeta_prev + G d_prev with the Gram matrix G = Z^T Z
 // (the same numbers without a second pass over the basis).
 // newton_only: skip the error bookkeeping (used after basis growth).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, const double* __restrict__ sums,
-                                                 int p, int slot, int two_d, int newton_only, int err_mode,
-                                                 int direct, double* __restrict__ hist, int hist_cap)
+__global__ __launch_bounds__(kThreads) void k_step_end(DevState* __restrict__ st, const double* __restrict__ sums,
+                                                       int p, int slot, int two_d, int newton_only, int err_mode,
+                                                       int direct, double* __restrict__ hist, int hist_cap)
 {
     __shared__ int sdone, snow, ssing;
     __shared__ double dprev[kMaxP], r[kMaxP];
+    __shared__ double Gs[kMaxP * kMaxP], Ai[kMaxP * kMaxP];
     const int t = threadIdx.x;
     if (t == 0) {
         sdone = st->done;
-        if (!sdone && !newton_only) {
+        ssing = st->singular;
+    }
+    __syncthreads();
+    if (sdone) return;  // uniform
+    // stage the small matrices while thread 0 does the bookkeeping
+    for (int e = t; e < p * p; e += kThreads) {
+        const int i = e / p, j = e - (e / p) * p;
+        if (!direct) Gs[i * kMaxP + j] = st->G[i * kMaxP + j];
+        Ai[i * kMaxP + j] = st->AinvT[i * kMaxP + j];
+    }
+    for (int j = t; j < p; j += kThreads) dprev[j] = st->d[j];
+    if (t == 0) {
+        if (!newton_only) {
             const double* s = st->sig_hat0;
             const double den = two_d ? (s[0] * s[0] + s[1] * s[1] + 2.0 * s[5] * s[5])
                                      : (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
@@ -1010,19 +1100,17 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
             }
         }
         snow = st->done;
-        ssing = st->singular;
     }
-    for (int j = t; j < p; j += 64) dprev[j] = st->d[j];
     __syncthreads();
-    if (sdone) return;
-    for (int i = t; i < p; i += 64) {
+    if (t < p) {
+        const int i = t;
         const double ze = sums[1 + i];
         double zz;
         if (direct) {
             zz = sums[1 + p + i];
         } else {
             zz = st->zeta[i];
-            for (int j = 0; j < p; ++j) zz += st->G[j * kMaxP + i] * dprev[j];
+            for (int j = 0; j < p; ++j) zz += Gs[j * kMaxP + i] * dprev[j];
         }
         st->zeta[i] = ze;
         st->z[i] = zz;
@@ -1030,7 +1118,7 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
         r[i] = ze - zz;
     }
     __syncthreads();
-    if (snow) return;
+    if (snow) return;  // uniform
     if (ssing) {
         if (t == 0) {
             st->status = 3;
@@ -1038,9 +1126,10 @@ __global__ __launch_bounds__(64) void k_finalize(DevState* __restrict__ st, cons
         }
         return;
     }
-    for (int i = t; i < p; i += 64) {
+    if (t < p) {
+        const int i = t;
         double y = 0.0;
-        for (int j = 0; j < p; ++j) y += st->AinvT[j * kMaxP + i] * r[j];
+        for (int j = 0; j < p; ++j) y += Ai[j * kMaxP + i] * r[j];
         st->d[i] = y - r[i];  // z' - zeta = (z + y) - zeta
     }
 }

@@ -27,10 +27,6 @@ constexpr size_t kAlign = 256;
 constexpr int kLdsCap = 60 * 1024;  // leaves room for static shared arrays
 constexpr int kMaxN = 512;
 constexpr double kFp32Stage = 1e-5;  // FP32 stage target before FP64 refinement
-#ifndef RPM_SPLIT_RECOMBINE
-#define RPM_SPLIT_RECOMBINE 1
-#endif
-constexpr bool kSplitRecombine = RPM_SPLIT_RECOMBINE != 0;  // recombination as its own pass
 #ifndef RPM_YPIPE
 #define RPM_YPIPE 1
 #endif
@@ -95,12 +91,12 @@ struct Shapes {
     Geo g;
     Plan px, py, pr;
     size_t lds_x, lds_y, lds_g;
-    int G1, Gy, G3, Gg, Gp, Gq;
+    int G1, Gy, Gyf, G3, Gg, Gp, Gq;  // Gyf: forward y-pass tiles (all spectral components)
     bool ok;
 };
 
 template <typename T>
-Shapes<T> make_shapes(const int32_t n[3])
+Shapes<T> make_shapes(const int32_t n[3], int ncomp)
 {
     Shapes<T> s{};
     const int wsz = (int)sizeof(cx<T>);
@@ -113,6 +109,7 @@ Shapes<T> make_shapes(const int32_t n[3])
     g.N = (long long)g.nx * g.ny * g.nz;
     g.nspec = (long long)g.nh * g.ny * g.nz;
     g.two_d = g.nz == 1 ? 1 : 0;
+    g.ncomp = ncomp;
     s.ok = true;
     // x passes: ty rows of nx, at most MV voxels per thread, 128-byte segments
     int tycap = std::min(128 / wsz, MV * kThreads / g.nx);
@@ -126,13 +123,13 @@ Shapes<T> make_shapes(const int32_t n[3])
     while (g.tz > 1 && (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz > (size_t)kLdsCap)
         g.tz = largest_divisor_leq(g.nz, g.tz - 1);
     s.lds_y = (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz;
-    // gamma pass: np pencils x 6 components along the last axis
+    // gamma pass: np pencils x ncomp components along the last axis
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
-    int np = 2;  // two pencils (x 6 components) per gamma tile: more resident tiles per CU
-    while (np > 1 && (size_t)(12 * np * lrow(nrow) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
+    int np = 2;  // two pencils per gamma tile: more resident tiles per CU
+    while (np > 1 && (size_t)(2 * ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
     g.np = np;
-    s.lds_g = (size_t)(12 * np * lrow(nrow) + nrow) * wsz + 80 * 8;
+    s.lds_g = (size_t)(2 * ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8;
     if (s.lds_x > (size_t)kLdsCap || s.lds_y > (size_t)kLdsCap || s.lds_g > (size_t)kLdsCap) s.ok = false;
     if (g.ty * g.nx > MV * kThreads) s.ok = false;
     g.fnx = make_fdiv(g.nx);
@@ -146,6 +143,7 @@ Shapes<T> make_shapes(const int32_t n[3])
     s.pr = make_plan(nrow);
     s.G1 = g.nz * (g.ny / g.ty);
     s.Gy = 6 * g.nh * (g.nz / g.tz);
+    s.Gyf = ncomp * g.nh * (g.nz / g.tz);
     s.G3 = (npen + g.np - 1) / g.np;
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
     s.Gp = (int)((6 * g.N + kVecBlock - 1) / kVecBlock);
@@ -172,7 +170,11 @@ rpm_options basic_fp64_options(const rpm_options* o)
 }
 
 template <typename T>
-Shapes<T> make_shapes(const int32_t n[3]);
+Shapes<T> make_shapes(const int32_t n[3], int ncomp);
+
+// Spectral components carried by the forward passes: sigma, and eps too for
+// the polarization iteration.
+int spectral_comps(const rpm_options* o) { return o->map == RPM_MAP_POLARIZATION ? 12 : 6; }
 
 template <typename T>
 Layout make_layout(const Shapes<T>& s, const rpm_options* o);
@@ -184,7 +186,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     const Geo& g = s.g;
     const size_t fT = (size_t)6 * g.N * sizeof(T);
     const size_t fD = (size_t)6 * g.N * sizeof(double);
-    const size_t spec = (size_t)6 * g.nspec * sizeof(cx<T>);
+    const size_t spec = (size_t)g.ncomp * g.nspec * sizeof(cx<T>);
     const int pmax = o->scheme == RPM_SCHEME_RPM ? o->p_max : 0;
     L.ld = kMaxP;
     L.hist_cap = (long long)o->max_iter + 1;
@@ -229,7 +231,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     if (fp32) {
         const int32_t n[3] = {g.nx, g.ny, g.nz};
         const rpm_options b = basic_fp64_options(o);
-        off = align_up(off + make_layout<double>(make_shapes<double>(n), &b).total);
+        off = align_up(off + make_layout<double>(make_shapes<double>(n, spectral_comps(&b)), &b).total);
     }
     L.total = off;
     return L;
@@ -304,6 +306,8 @@ struct Ctx {
     const uint8_t* phase;
     double lam0, mu0;
     int pmax;
+    bool pol = false;             // polarization iteration in place of F
+    double alpha = 2.0, beta = 2.0;
     Prof prof;
     bool hip_error = false;
 
@@ -361,8 +365,9 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     const double specB = 6.0 * (double)g.nspec * sizeof(cx<T>);
     const double bi = specB + fieldB * (2 + (shift ? 1 : 0));
     hipEvent_t ev;
-    if (p_corr > 0 && kSplitRecombine) {
-        // eps = xin + Z d as its own streaming pass; the x pass then reads eps
+    if (eps_store) {
+        // eps = xin + Z d (a copy while p = 0) as its own streaming pass; the x
+        // pass then reads eps
         const long long nel = 6 * g.N;
         const int VL = 16 / (int)sizeof(T);
         const int gb = (int)((nel / VL + kThreads - 1) / kThreads) + 1;
@@ -370,33 +375,44 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         k_recombine<T><<<gb, kThreads, 0, c.s>>>(xin, c.Zb(), p_corr, c.pmax, c.st->d, eps_store, nel, done);
         c.mark_end(RPM_K_RECOMBINE, ev, fieldB * (2 + p_corr));
         xin = eps_store;
-        p_corr = 0;
-        eps_store = nullptr;
     }
-    const double bx = fieldB * (1 + p_corr + (eps_store ? 1 : 0)) + (use_ref ? 0.0 : (double)g.N) + specB;
+    const double cf = (double)g.ncomp / 6.0;  // spectral components carried forward, over 6
+    const double bx = fieldB + (use_ref ? 0.0 : (double)g.N) + cf * specB;
+    const bool pol = c.pol && out_mode == OUT_XI;
     c.mark_begin(RPM_K_XFWD, ev);
-    if (g.nx % (16 / (int)sizeof(T)) == 0)
-        k_xfwd<T, true><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zb() : nullptr, p_corr, c.pmax, c.st->d,
-                                                            eps_store, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1,
-                                                            pmean, g, sh.px, c.twx(), done);
-    else
-        k_xfwd<T, false><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, p_corr ? c.Zb() : nullptr, p_corr, c.pmax, c.st->d,
-                                                             eps_store, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1,
-                                                             pmean, g, sh.px, c.twx(), done);
+    const bool vec = g.nx % (16 / (int)sizeof(T)) == 0;
+#define RPM_XFWD(V, P)                                                                                         \
+    k_xfwd<T, V, P><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, \
+                                                        g, sh.px, c.twx(), done)
+    if (pol) {
+        if (vec) RPM_XFWD(true, true);
+        else RPM_XFWD(false, true);
+    } else {
+        if (vec) RPM_XFWD(true, false);
+        else RPM_XFWD(false, false);
+    }
+#undef RPM_XFWD
     c.mark_end(RPM_K_XFWD, ev, bx);
     if (!g.two_d) {
+        const int tiles = pol ? sh.Gyf : sh.Gy;
         c.mark_begin(RPM_K_YFWD, ev);
         if (kYPipe && g.tz * g.ny <= 8 * kThreads)
-            k_ypipe<T, -1, 8><<<std::min(sh.Gy, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
-                                                                                           c.twy(), sh.Gy, done);
+            k_ypipe<T, -1, 8><<<std::min(tiles, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
+                                                                                            c.twy(), tiles, done);
         else
-            k_yfwd<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
-        c.mark_end(RPM_K_YFWD, ev, 2.0 * specB);
+            k_yfwd<T><<<tiles, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
+        c.mark_end(RPM_K_YFWD, ev, 2.0 * (pol ? cf : 1.0) * specB);
     }
     c.mark_begin(RPM_K_GAMMA, ev);
-    k_gamma<T><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0, dc_mode,
-                                                   Edev, pmean, sh.G1, perr, c.st, done);
-    c.mark_end(RPM_K_GAMMA, ev, 2.0 * specB);
+    if (pol)
+        k_gamma<T, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0,
+                                                             c.alpha, c.beta, dc_mode, Edev, pmean, sh.G1, perr,
+                                                             c.st, done);
+    else
+        k_gamma<T, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0,
+                                                              c.alpha, c.beta, dc_mode, Edev, pmean, sh.G1, perr,
+                                                              c.st, done);
+    c.mark_end(RPM_K_GAMMA, ev, ((pol ? cf : 1.0) + 1.0) * specB);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
         if (kYPipe && g.tz * g.ny <= 8 * kThreads)
@@ -407,20 +423,25 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         c.mark_end(RPM_K_YINV, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_XINV, ev);
-    k_xinv<T><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,
-                                                  c.twx(), done);
-    c.mark_end(RPM_K_XINV, ev, bi);
+    if (pol)
+        k_xinv<T, true><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,
+                                                            c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta, done);
+    else
+        k_xinv<T, false><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g,
+                                                             sh.px, c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta,
+                                                             done);
+    c.mark_end(RPM_K_XINV, ev, bi + (pol ? (double)g.N : 0.0));
     c.check_launch();
 }
 
 // Products <Z_j, a_f> (j < p) with the tiled basis: column-major partials
 // part[(f * ld + j) * G + b], one wave per group of 8 columns.
-template <typename TA, typename TZ, int NF>
+template <typename TA, typename TZ, int NF, int SITE>
 void launch_gdots(hipStream_t s, int G, const TA* a0, const TA* a1, const TZ* Z, int p, int zP, long long N,
                   double* part, int ld)
 {
     const int ng = (p + 7) / 8;
-    k_gdots<TA, TZ, NF><<<G, 64 * ng, 0, s>>>(a0, a1, Z, p, zP, N, part, ld);
+    k_gdots<TA, TZ, NF, SITE><<<G, 64 * ng, 0, s>>>(a0, a1, Z, p, zP, N, part, ld);
 }
 
 // v <- v - sum_j coef_j Z_j, then the products <Z_j, v> (and, NRM, <v, v>):
@@ -447,9 +468,9 @@ void project(Ctx<T>& c, const T* xi, const T* eps, int p, bool direct)
     hipEvent_t ev;
     c.mark_begin(RPM_K_PROJECT, ev);
     if (direct)
-        launch_gdots<T, T, 2>(c.s, c.sh.Gq, xi, eps, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+        launch_gdots<T, T, 2, 0>(c.s, c.sh.Gq, xi, eps, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
     else
-        launch_gdots<T, T, 1>(c.s, c.sh.Gq, xi, nullptr, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+        launch_gdots<T, T, 1, 0>(c.s, c.sh.Gq, xi, nullptr, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
     c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * ((direct ? 2 : 1) + p));
 }
 
@@ -468,8 +489,8 @@ void reduce_and_finalize(Ctx<T>& c, int p, int slot, int newton_only, bool direc
                                                     c.L.ld, p, c.sums(), done);
     c.mark_end(RPM_K_REDUCE, ev);
     c.mark_begin(RPM_K_FINAL, ev);
-    k_finalize<<<1, 64, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only, err_mode, direct ? 1 : 0,
-                                 c.template at<double>(c.L.hist), (int)c.L.hist_cap);
+    k_step_end<<<1, kThreads, 0, c.s>>>(c.st, c.sums(), p, slot & 3, c.sh.g.two_d, newton_only, err_mode,
+                                        direct ? 1 : 0, c.template at<double>(c.L.hist), (int)c.L.hist_cap);
     c.mark_end(RPM_K_FINAL, ev);
     c.check_launch();
 }
@@ -601,12 +622,17 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         const double nrm = col == 0 ? T11 : T22;
         if (!(nrm > 0.0)) continue;
         if (col == 1 && !two) continue;
-        // normalise, project onto zero-mean compatible fields, back to FP64
+        // normalise, project onto zero-mean compatible fields (Lippmann-Schwinger map), back to FP64
         const long long nel = 6 * N;
         const int gb = (int)((nel + 255) / 256);
         k_convert<double, T><<<gb, 256, 0, c.s>>>(v, tmp, 1.0 / nrm, nel);
-        project_compatible<T>(c, tmp, tmp2);
-        k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
+        if (c.pol) {
+            // polarization iterates are not compatible: the differences stay as they are
+            k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp, v, 1.0, nel);
+        } else {
+            project_compatible<T>(c, tmp, tmp2);
+            k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
+        }
         // two classical Gram-Schmidt passes against Z: coefficients; the update fused
         // with the second coefficients; the second update fused with the norm
         const int Gq = c.sh.Gq;
@@ -614,7 +640,7 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         double* coef = c.gsum();
         double* coef2 = c.sums() + kMaxP + 2;
         if (p > 0) {
-            launch_gdots<double, T, 1>(c.s, Gq, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), kMaxP);
+            launch_gdots<double, T, 1, 1>(c.s, Gq, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), kMaxP);
             reduce_cols(c, c.pg(), Gq, 1, Gq, p, coef);
             launch_update<T, false>(c.s, Gq, v, c.Zb(), p, c.pmax, coef, N, c.pg(), rs);
             reduce_cols(c, c.pg(), Gq, rs, 1, p, coef2);
@@ -633,13 +659,13 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
         // column p of H, <z_i, w> (i <= p), and of the Gram matrix, <z_i, z_p>, in one pass
         double* hcol = c.sums() + 1;
         double* gram = c.sums() + kMaxP + 2;
-        launch_gdots<T, T, 2>(c.s, Gq, tmp2, tmp, c.Zb(), p + 1, c.pmax, N, c.pg(), kMaxP);
+        launch_gdots<T, T, 2, 1>(c.s, Gq, tmp2, tmp, c.Zb(), p + 1, c.pmax, N, c.pg(), kMaxP);
         reduce_cols(c, c.pg(), Gq, 1, Gq, p + 1, hcol);
         reduce_cols(c, c.pg() + (long long)kMaxP * Gq, Gq, 1, Gq, p + 1, gram);
         // new row: <z_p, w_j> for j < p
         double* row = c.gsum();
         if (p > 0) {
-            launch_gdots<T, T, 1>(c.s, Gq, tmp, nullptr, c.Wb(), p, c.pmax, N, c.pg(), kMaxP);
+            launch_gdots<T, T, 1, 1>(c.s, Gq, tmp, nullptr, c.Wb(), p, c.pmax, N, c.pg(), kMaxP);
             reduce_cols(c, c.pg(), Gq, 1, Gq, p, row);
         }
         k_border<<<1, 1, 0, c.s>>>(c.st, hcol, row, gram, p);
@@ -777,7 +803,7 @@ void sub64_init(Ctx<double>& c64, Ctx<float>& c, const rpm_options* o)
 {
     const int32_t n[3] = {c.sh.g.nx, c.sh.g.ny, c.sh.g.nz};
     const rpm_options b = basic_fp64_options(o);
-    c64.sh = make_shapes<double>(n);
+    c64.sh = make_shapes<double>(n, spectral_comps(&b));
     c64.L = make_layout<double>(c64.sh, &b);
     c64.s = c.s;
     c64.ws = c.ws + c.L.sub64;
@@ -786,6 +812,9 @@ void sub64_init(Ctx<double>& c64, Ctx<float>& c, const rpm_options* o)
     c64.lam0 = c.lam0;
     c64.mu0 = c.mu0;
     c64.pmax = 0;
+    c64.pol = c.pol;
+    c64.alpha = c.alpha;
+    c64.beta = c.beta;
     c64.prof.on = false;
 }
 
@@ -924,6 +953,10 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->replay_len < 0 || (o->replay_len > 0 && !o->replay)) return RPM_E_INVALID;
     if (o->refine < 0 || !finite(o->refine_tol) || !(o->refine_tol > 0.0) || !(o->refine_tol < 1.0))
         return RPM_E_INVALID;
+    if (o->map != RPM_MAP_LS && o->map != RPM_MAP_POLARIZATION) return RPM_E_INVALID;
+    if (o->map == RPM_MAP_POLARIZATION &&
+        (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
+        return RPM_E_INVALID;
     return RPM_OK;
 }
 
@@ -931,8 +964,10 @@ template <typename T>
 rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void* ws, size_t ws_bytes,
                     void* stream)
 {
-    c.sh = make_shapes<T>(pr->n);
+    c.sh = make_shapes<T>(pr->n, spectral_comps(o));
     if (!c.sh.ok) return RPM_E_UNSUPPORTED_SIZE;
+    // FP32 fields are certified by an FP64 pipeline on the same grid
+    if (sizeof(T) == 4 && !make_shapes<double>(pr->n, spectral_comps(o)).ok) return RPM_E_UNSUPPORTED_SIZE;
     c.L = make_layout<T>(c.sh, o);
     if (!ws || ws_bytes < c.L.total) return RPM_E_WORKSPACE;
     if (!pr->phase) return RPM_E_INVALID;
@@ -943,6 +978,9 @@ rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void
     c.lam0 = pr->lame0[0];
     c.mu0 = pr->lame0[1];
     c.pmax = o->scheme == RPM_SCHEME_RPM ? o->p_max : 0;
+    c.pol = o->map == RPM_MAP_POLARIZATION;
+    c.alpha = o->alpha;
+    c.beta = o->beta;
     c.prof.on = o->profile != 0;
     return RPM_OK;
 }
@@ -1037,6 +1075,9 @@ void rpm_default_options(rpm_options* o)
     o->profile = 0;
     o->refine = 4;
     o->refine_tol = 1e-3;
+    o->map = RPM_MAP_LS;
+    o->alpha = 2.0;
+    o->beta = 2.0;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
@@ -1055,13 +1096,14 @@ rpm_status rpm_workspace_size(const int32_t n[3], const rpm_options* o, size_t* 
         if (n[a] < 2 || n[a] > kMaxN || !smooth23(n[a])) return RPM_E_UNSUPPORTED_SIZE;
     }
     if (o->max_iter < 1 || o->p_max < 0 || o->p_max > kMaxP) return RPM_E_INVALID;
+    if (o->map != RPM_MAP_LS && o->map != RPM_MAP_POLARIZATION) return RPM_E_INVALID;
     if (o->precision == RPM_FP64) {
-        Shapes<double> s = make_shapes<double>(n);
+        Shapes<double> s = make_shapes<double>(n, spectral_comps(o));
         if (!s.ok) return RPM_E_UNSUPPORTED_SIZE;
         *bytes = make_layout<double>(s, o).total;
     } else if (o->precision == RPM_FP32) {
-        Shapes<float> s = make_shapes<float>(n);
-        if (!s.ok) return RPM_E_UNSUPPORTED_SIZE;
+        Shapes<float> s = make_shapes<float>(n, spectral_comps(o));
+        if (!s.ok || !make_shapes<double>(n, spectral_comps(o)).ok) return RPM_E_UNSUPPORTED_SIZE;
         *bytes = make_layout<float>(s, o).total;
     } else {
         return RPM_E_INVALID;

@@ -36,6 +36,19 @@ def disk_2d(n, radius_frac=0.25):
     return ph.reshape(1, n, n)
 
 
+def workload_fibre(K, n=128, radius_frac=0.25):
+    """The circular-fibre cell of Sec. 5 as used for the contrast sweep of Sec. 5.5
+    (Table 1, whose grid and fibre size are not stated): n x n plane strain, a
+    centred stiff fibre (radius radius_frac * n) of modulus K in a matrix of
+    modulus 1, nu = 0.25 in both, mean shear strain eps_12 = 0.5 % (tensor
+    component), reference medium at the geometric mean of the two moduli,
+    tolerance 1e-4."""
+    E = np.zeros(6)
+    E[5] = 0.005
+    return dict(phase=disk_2d(n, radius_frac), phases=[(1.0, 0.25), (float(K), 0.25)], E=E,
+                ref=(float(np.sqrt(K)), 0.25), tol=1e-4)
+
+
 def rsa_spheres(n, r_min, r_max, vf_target, seed, gap=1.0, max_tries=200000):
     """Periodic n^3 phase map with non-overlapping spheres (phase 1) in phase 0.
 

@@ -42,6 +42,7 @@ def test_default_options_and_status_strings(B):
     o = B.make_options()
     assert o.tol == 1e-6 and o.max_iter == 10000 and o.n_max == 10 and o.p_max == 32
     assert abs(o.kappa - 0.1) < 1e-15 and o.scheme == 1 and o.precision == 0 and o.check_every == 16
+    assert o.map == 0 and o.alpha == 2.0 and o.beta == 2.0
     for code, name in B.STATUS.items():
         assert B.status_string(code) == name
     assert B.status_string(99) == "RPM_UNKNOWN"
@@ -71,6 +72,13 @@ def test_workspace_size_rules(B):
     assert B.workspace_size((32, 32, 32), B.make_options(precision="fp32")) < B.workspace_size((32, 32, 32), o)
     with pytest.raises(B.RpmError):
         B.workspace_size((8, 8, 8), B.make_options(p_max=65))
+    # the polarization iteration carries eps through the forward passes: twice the spectra
+    sp = B.workspace_size((32, 32, 32), B.make_options(map="polarization"))
+    assert sp >= B.workspace_size((32, 32, 32), o) + 2 * 6 * 17 * 32 * 32 * 16
+    # its 12-component gamma tiles bound the FP64 pencil length (FP32 certifies in FP64)
+    with pytest.raises(B.RpmError) as e:
+        B.workspace_size((256, 8, 8), B.make_options(map="polarization"))
+    assert e.value.code == -2
 
 
 def _raw_problem(B, n=(8, 8, 8), lame=((1.0, 1.0),), lame0=(1.0, 1.0)):
@@ -86,7 +94,7 @@ def _raw_problem(B, n=(8, 8, 8), lame=((1.0, 1.0),), lame0=(1.0, 1.0)):
 
 
 @pytest.mark.parametrize("case", ["tol", "nan_E", "pmax", "mu0", "neg_mu", "scheme", "check", "size", "nphase",
-                                  "workspace", "kappa", "replay"])
+                                  "workspace", "kappa", "replay", "map", "alpha"])
 def test_solve_rejects_bad_arguments_before_device_work(B, case):
     lib = B._lib
     o = B.make_options()
@@ -118,6 +126,11 @@ def test_solve_rejects_bad_arguments_before_device_work(B, case):
         expect = -3
     elif case == "kappa":
         o.kappa = 1.5
+    elif case == "map":
+        o.map = 3
+    elif case == "alpha":
+        o.map = 1
+        o.alpha = -1.0
     elif case == "replay":
         o.replay_len = 3
     rc = lib.rpm_fft_solve(ctypes.byref(pr), E, ctypes.byref(o), None, None, None, None, None, ws, wsb, None)
