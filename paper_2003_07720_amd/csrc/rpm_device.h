@@ -14,7 +14,7 @@ constexpr int kMaxStages = 10;
 constexpr int kMaxP = 64;         // basis cap
 
 template <typename T>
-struct cx {
+struct __align__(2 * sizeof(T)) cx {
     T x, y;
 };
 
@@ -225,12 +225,12 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
 // (power-of-two lengths): index arithmetic reduces to shifts and masks.
 template <typename T, int R, int D, int N, int NS>
 __device__ __forceinline__ void fft_stage_ct(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int nseq,
-                                             int ss, const cx<T>* __restrict__ tw)
+                                             int ss, const cx<T>* __restrict__ tw, int tid)
 {
     constexpr int nb = N / R;
     constexpr int tws = N / (NS * R);
     const int total = nb * nseq;
-    for (int g = threadIdx.x; g < total; g += kThreads) {
+    for (int g = tid; g < total; g += kThreads) {
         const int s = g / nb;
         const int j = g & (nb - 1);
         const cx<T>* in = src + s * ss;
@@ -261,15 +261,15 @@ constexpr int ct_nst(int n) { return ct_log2(n) / 4 + (ct_log2(n) % 4 ? 1 : 0); 
 constexpr int ct_rad(int n, int st) { return st < ct_log2(n) / 4 ? 16 : (1 << (ct_log2(n) % 4)); }
 
 template <typename T, int D, int N, int ST, int NS>
-__device__ __forceinline__ cx<T>* ct_stages(cx<T>* src, cx<T>* dst, int nseq, int ss, const cx<T>* tw)
+__device__ __forceinline__ cx<T>* ct_stages(cx<T>* src, cx<T>* dst, int nseq, int ss, const cx<T>* tw, int tid)
 {
     if constexpr (ST == ct_nst(N)) {
         return src;
     } else {
         constexpr int R = ct_rad(N, ST);
-        fft_stage_ct<T, R, D, N, NS>(src, dst, nseq, ss, tw);
+        fft_stage_ct<T, R, D, N, NS>(src, dst, nseq, ss, tw, tid);
         __syncthreads();
-        return ct_stages<T, D, N, ST + 1, NS * R>(dst, src, nseq, ss, tw);
+        return ct_stages<T, D, N, ST + 1, NS * R>(dst, src, nseq, ss, tw, tid);
     }
 }
 
@@ -277,9 +277,10 @@ __device__ __forceinline__ cx<T>* ct_stages(cx<T>* src, cx<T>* dst, int nseq, in
 // Caller must __syncthreads() after filling a.  Returns the buffer that holds
 // the natural-order result; all threads are synchronised on return.
 template <typename T, int D>
-__device__ cx<T>* lds_fft(cx<T>* a, cx<T>* b, const Plan& pl, int nseq, int ss, const cx<T>* tw)
+__device__ cx<T>* lds_fft(cx<T>* a, cx<T>* b, const Plan& pl, int nseq, int ss, const cx<T>* tw,
+                         int tid = threadIdx.x)
 {
-    if (pl.n == 128) return ct_stages<T, D, 128, 0, 1>(a, b, nseq, ss, tw);
+    if (pl.n == 128) return ct_stages<T, D, 128, 0, 1>(a, b, nseq, ss, tw, tid);
     int Ns = 1;
     cx<T>* src = a;
     cx<T>* dst = b;

@@ -34,6 +34,7 @@ struct Geo {
     int two_d;
     int ncomp;             // spectral components of the forward passes (6, or 12 with eps)
     FDiv fnx, fny, fnh, fty, ftz, frow;  // divisions by nx, ny, nh, ty, tz and the gamma row length
+    double kh[3];          // 2 pi / n per axis (wave number of index 1)
 };
 
 // Basis storage: Z (and W = F_u Z) in tiles of kZTile consecutive elements of
@@ -394,20 +395,21 @@ __device__ __forceinline__ void wave_vector(int kx, int ky, int kz, const Geo& g
 {
     const int m[3] = {kx, ky, kz};
     const int n[3] = {g.nx, g.ny, g.nz};
-    int sgn = 1;
-    bool ny_[3];
-    int s_[3];
+    bool nyq[3];
+    int sv[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        ny_[a] = ((n[a] & 1) == 0) && (2 * m[a] == n[a]);
-        s_[a] = (2 * m[a] < n[a] + 1) ? m[a] : m[a] - n[a];
+        nyq[a] = ((n[a] & 1) == 0) && (2 * m[a] == n[a]);
+        sv[a] = (2 * m[a] <= n[a]) ? m[a] : m[a] - n[a];
     }
-    if (!ny_[2] && s_[2] != 0) sgn = s_[2] > 0 ? 1 : -1;
-    else if (!ny_[1] && s_[1] != 0) sgn = s_[1] > 0 ? 1 : -1;
-    else if (!ny_[0] && s_[0] != 0) sgn = s_[0] > 0 ? 1 : -1;
+    // later axes override earlier ones: z decides first, then y, then x
+    int sgn = 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!nyq[a] && sv[a] != 0) sgn = sv[a] > 0 ? 1 : -1;
     const double pi = 3.14159265358979323846;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) k[a] = ny_[a] ? -pi * sgn : 2.0 * pi * (double)s_[a] / (double)n[a];
+    for (int a = 0; a < 3; ++a) k[a] = nyq[a] ? -pi * sgn : (double)sv[a] * g.kh[a];
 }
 
 // ---------------------------------------------------------------------------
@@ -423,6 +425,123 @@ __device__ __forceinline__ void wave_vector(int kx, int ky, int kz, const Geo& g
 // 3-D: rows along z of S2 (pencil = ky * nh + kx).  2-D: rows along y of S1
 // (pencil = kx, kz = 0).  grid: ceil(npencils / np).
 // ---------------------------------------------------------------------------
+// Green operator at one frequency of a gamma tile: component c of the pencil
+// sits in row c * nrs + r of R (element i).  Overwrites components 0..5 with
+// t_hat (the k = 0 entry as described above) and returns the frequency's share
+// of the equilibrium error.
+template <typename T, bool POL>
+__device__ __forceinline__ double gamma_point(cx<T>* R, int ss, int nrs, int r, int i, int kx, int ky, int kz,
+                                              const Geo& g, double lam0, double mu0, double alpha, double beta,
+                                              int dc_mode, const double* __restrict__ E, const double* dc_mean,
+                                              DevState* __restrict__ st)
+{
+    cx<T> s[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s[c] = R[(c * nrs + r) * ss + lpad(i)];
+    // the field the Green operator acts on: sigma_hat, or s_b (POL)
+    cx<T> sg[6];
+    if constexpr (POL) {
+        cx<T> e[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] = R[((6 + c) * nrs + r) * ss + lpad(i)];
+        const cx<T> tr = cadd(cadd(e[0], e[1]), e[2]);
+        const T al = (T)alpha, bl = (T)(beta * lam0), b2m = (T)(2.0 * beta * mu0);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            cx<T> v = csub(cscale(s[c], al), cscale(e[c], b2m));
+            if (c < 3) v = csub(v, cscale(tr, bl));
+            sg[c] = v;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sg[c] = s[c];
+    }
+    double esum = 0.0;
+    cx<T> o[6];
+    if (kx == 0 && ky == 0 && kz == 0) {
+        const double Nd = (double)g.N;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            st->sig_hat0[c] = (double)s[c].x;
+            st->mean_eps[c] = dc_mean[c] / Nd;
+            double v;
+            if constexpr (POL) v = (dc_mode == DC_MEAN) ? -Nd * beta * E[c] : 0.0;
+            else v = (dc_mode == DC_MEAN) ? (dc_mean[c] - Nd * E[c]) : 0.0;
+            o[c] = cx<T>{(T)v, T(0)};
+        }
+    } else {
+        const double c0 = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
+        const double imu = 1.0 / mu0;
+        double k[3];
+        wave_vector(kx, ky, kz, g, k);
+        const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        T n0, n1, n2;
+        if constexpr (sizeof(T) == 4) {
+            // FP32 fields: the unit direction to FP32 accuracy is all the filter uses
+            const float ik = rsqrtf((float)kk);
+            n0 = (float)k[0] * ik;
+            n1 = (float)k[1] * ik;
+            n2 = (float)k[2] * ik;
+        } else {
+            const double ik = 1.0 / sqrt(kk);
+            n0 = k[0] * ik;
+            n1 = k[1] * ik;
+            n2 = k[2] * ik;
+        }
+        // s = sigma_hat n with components xx,yy,zz,yz,xz,xy = 0..5
+        cx<T> sx = cadd(cadd(cscale(s[0], n0), cscale(s[5], n1)), cscale(s[4], n2));
+        cx<T> sy = cadd(cadd(cscale(s[5], n0), cscale(s[1], n1)), cscale(s[3], n2));
+        cx<T> sz = cadd(cadd(cscale(s[4], n0), cscale(s[3], n1)), cscale(s[2], n2));
+        const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+        const T s2 = sx.x * sx.x + sx.y * sx.y + sy.x * sy.x + sy.y * sy.y + sz.x * sz.x + sz.y * sz.y;
+        esum = w * kk * (double)s2;
+        if constexpr (POL) {
+            sx = cadd(cadd(cscale(sg[0], n0), cscale(sg[5], n1)), cscale(sg[4], n2));
+            sy = cadd(cadd(cscale(sg[5], n0), cscale(sg[1], n1)), cscale(sg[3], n2));
+            sz = cadd(cadd(cscale(sg[4], n0), cscale(sg[3], n1)), cscale(sg[2], n2));
+        }
+        const cx<T> a = cadd(cadd(cscale(sx, n0), cscale(sy, n1)), cscale(sz, n2));
+        const T m1 = (T)imu, cc = (T)c0, hm = T(0.5) * (T)imu;
+        o[0] = csub(cscale(sx, m1 * n0), cscale(a, cc * n0 * n0));
+        o[1] = csub(cscale(sy, m1 * n1), cscale(a, cc * n1 * n1));
+        o[2] = csub(cscale(sz, m1 * n2), cscale(a, cc * n2 * n2));
+        o[3] = csub(cadd(cscale(sz, hm * n1), cscale(sy, hm * n2)), cscale(a, cc * n1 * n2));
+        o[4] = csub(cadd(cscale(sz, hm * n0), cscale(sx, hm * n2)), cscale(a, cc * n0 * n2));
+        o[5] = csub(cadd(cscale(sy, hm * n0), cscale(sx, hm * n1)), cscale(a, cc * n0 * n1));
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) R[(c * nrs + r) * ss + lpad(i)] = o[c];
+    return esum;
+}
+
+// Frequency indices of element i of gamma pencil pen.
+__device__ __forceinline__ void gamma_freq(const Geo& g, int pen, int i, int& kx, int& ky, int& kz)
+{
+    if (g.two_d) {
+        kx = pen;
+        ky = i;
+        kz = 0;
+    } else {
+        ky = g.fnh.div(pen);
+        kx = pen - ky * g.nh;
+        kz = i;
+    }
+}
+
+// <eps> from the x-pass partial sums (block 0 of a gamma launch holds k = 0).
+__device__ __forceinline__ void gamma_dc_mean(int dc_mode, const double* __restrict__ part_mean, int n_mean,
+                                              double* dc_mean, double* red)
+{
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (dc_mode == DC_MEAN) {
+        for (int b = threadIdx.x; b < n_mean; b += kThreads) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[c] += part_mean[(long long)b * 6 + c];
+        }
+    }
+    wg_sum_store<6>(acc, dc_mean, red);
+}
+
 template <typename T, bool POL>
 __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g, Plan pr,
                                                     const cx<T>* __restrict__ twr, double lam0, double mu0,
@@ -455,101 +574,19 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
             A[(c * npl + pl) * ss + lpad(i)] = src[t];
         }
     }
-    // block 0 holds the k = 0 frequency: finish <eps> from the xfwd partials
     __shared__ double dc_mean[6];
-    if (blockIdx.x == 0) {
-        double acc[6] = {0, 0, 0, 0, 0, 0};
-        if (dc_mode == DC_MEAN) {
-            for (int b = threadIdx.x; b < n_mean; b += kThreads) {
-#pragma unroll
-                for (int c = 0; c < 6; ++c) acc[c] += part_mean[(long long)b * 6 + c];
-            }
-        }
-        wg_sum_store<6>(acc, dc_mean, red);
-    }
+    if (blockIdx.x == 0) gamma_dc_mean(dc_mode, part_mean, n_mean, dc_mean, red);
     __syncthreads();
     cx<T>* R = lds_fft<T, -1>(A, B, pr, NC * npl, ss, tw);
 
-    const double c0 = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0));
-    const double imu = 1.0 / mu0;
     double esum = 0.0;
     for (int t = threadIdx.x; t < npl * nrow; t += kThreads) {
         const int pl = g.frow.div(t);
         const int i = t - pl * nrow;
-        const int pen = p0 + pl;
         int kx, ky, kz;
-        if (g.two_d) {
-            kx = pen;
-            ky = i;
-            kz = 0;
-        } else {
-            ky = g.fnh.div(pen);
-            kx = pen - ky * g.nh;
-            kz = i;
-        }
-        cx<T> s[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) s[c] = R[(c * npl + pl) * ss + lpad(i)];
-        // the field the Green operator acts on: sigma_hat, or s_b (POL)
-        cx<T> sg[6];
-        if constexpr (POL) {
-            cx<T> e[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) e[c] = R[((6 + c) * npl + pl) * ss + lpad(i)];
-            const cx<T> tr = cadd(cadd(e[0], e[1]), e[2]);
-            const T al = (T)alpha, bl = (T)(beta * lam0), b2m = (T)(2.0 * beta * mu0);
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                cx<T> v = csub(cscale(s[c], al), cscale(e[c], b2m));
-                if (c < 3) v = csub(v, cscale(tr, bl));
-                sg[c] = v;
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < 6; ++c) sg[c] = s[c];
-        }
-        cx<T> o[6];
-        if (kx == 0 && ky == 0 && kz == 0) {
-            const double Nd = (double)g.N;
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                st->sig_hat0[c] = (double)s[c].x;
-                st->mean_eps[c] = dc_mean[c] / Nd;
-                double v;
-                if constexpr (POL) v = (dc_mode == DC_MEAN) ? -Nd * beta * E[c] : 0.0;
-                else v = (dc_mode == DC_MEAN) ? (dc_mean[c] - Nd * E[c]) : 0.0;
-                o[c] = cx<T>{(T)v, T(0)};
-            }
-        } else {
-            double k[3];
-            wave_vector(kx, ky, kz, g, k);
-            const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
-            const double ik = 1.0 / sqrt(kk);
-            const T n0 = (T)(k[0] * ik), n1 = (T)(k[1] * ik), n2 = (T)(k[2] * ik);
-            // s = sigma_hat n with components xx,yy,zz,yz,xz,xy = 0..5
-            cx<T> sx = cadd(cadd(cscale(s[0], n0), cscale(s[5], n1)), cscale(s[4], n2));
-            cx<T> sy = cadd(cadd(cscale(s[5], n0), cscale(s[1], n1)), cscale(s[3], n2));
-            cx<T> sz = cadd(cadd(cscale(s[4], n0), cscale(s[3], n1)), cscale(s[2], n2));
-            const double w = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
-            esum += w * kk *
-                    ((double)sx.x * sx.x + (double)sx.y * sx.y + (double)sy.x * sy.x + (double)sy.y * sy.y +
-                     (double)sz.x * sz.x + (double)sz.y * sz.y);
-            if constexpr (POL) {
-                sx = cadd(cadd(cscale(sg[0], n0), cscale(sg[5], n1)), cscale(sg[4], n2));
-                sy = cadd(cadd(cscale(sg[5], n0), cscale(sg[1], n1)), cscale(sg[3], n2));
-                sz = cadd(cadd(cscale(sg[4], n0), cscale(sg[3], n1)), cscale(sg[2], n2));
-            }
-            const cx<T> a = cadd(cadd(cscale(sx, n0), cscale(sy, n1)), cscale(sz, n2));
-            const T m1 = (T)imu, cc = (T)c0, hm = T(0.5) * (T)imu;
-            o[0] = csub(cscale(sx, m1 * n0), cscale(a, cc * n0 * n0));
-            o[1] = csub(cscale(sy, m1 * n1), cscale(a, cc * n1 * n1));
-            o[2] = csub(cscale(sz, m1 * n2), cscale(a, cc * n2 * n2));
-            o[3] = csub(cadd(cscale(sz, hm * n1), cscale(sy, hm * n2)), cscale(a, cc * n1 * n2));
-            o[4] = csub(cadd(cscale(sz, hm * n0), cscale(sx, hm * n2)), cscale(a, cc * n0 * n2));
-            o[5] = csub(cadd(cscale(sy, hm * n0), cscale(sx, hm * n1)), cscale(a, cc * n0 * n1));
-        }
-#pragma unroll
-        for (int c = 0; c < 6; ++c) R[(c * npl + pl) * ss + lpad(i)] = o[c];
+        gamma_freq(g, p0 + pl, i, kx, ky, kz);
+        esum += gamma_point<T, POL>(R, ss, npl, pl, i, kx, ky, kz, g, lam0, mu0, alpha, beta, dc_mode, E, dc_mean,
+                                    st);
     }
     __syncthreads();
     const cx<T>* Q = lds_fft<T, +1>(R, R == A ? B : A, pr, nseq, ss, tw);
@@ -559,6 +596,84 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
             const int pl = g.frow.div(t);
             const int i = t - pl * nrow;
             dst[t] = Q[(c * npl + pl) * ss + lpad(i)];
+        }
+    }
+    double ev[1] = {esum};
+    if (part_err) wg_sum_store<1>(ev, part_err + blockIdx.x, red);
+}
+
+// Software-pipelined gamma pass for tiles of exactly kThreads elements per
+// component (g.np pencils of nrow = kThreads / g.np): a persistent grid walks
+// the tiles; each thread holds its element of every component of the next
+// tile in registers, in flight while the current tile is transformed,
+// filtered and stored.  Pencils past the last one are zero and never stored.
+// part_err gets one sum per block.
+template <typename T, bool POL>
+__global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g, Plan pr,
+                                                    const cx<T>* __restrict__ twr, double lam0, double mu0,
+                                                    double alpha, double beta, int dc_mode,
+                                                    const double* __restrict__ E,
+                                                    const double* __restrict__ part_mean, int n_mean,
+                                                    double* __restrict__ part_err, DevState* __restrict__ st,
+                                                    int ntiles, const int* __restrict__ done)
+{
+    if (done && *done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int NC = POL ? 12 : 6;
+    const int np = g.np;
+    const int nrow = g.two_d ? g.ny : g.nz;
+    const long long nlast = (long long)(g.two_d ? g.nh : g.ny * g.nh) * nrow;  // elements per component
+    const int ss = lrow(nrow);
+    cx<T>* A0 = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* B0 = A0 + NC * np * ss;
+    cx<T>* tw0 = B0 + NC * np * ss;
+    double* red = reinterpret_cast<double*>(tw0 + nrow);
+
+    for (int i = threadIdx.x; i < nrow; i += kThreads) tw0[i] = twr[i];
+    __shared__ double dc_mean[6];
+    if (blockIdx.x == 0) gamma_dc_mean(dc_mode, part_mean, n_mean, dc_mean, red);
+    // this thread's element of a tile: pencil pl, row element i
+    const int pl = g.frow.div(threadIdx.x);
+    const int i = threadIdx.x - pl * nrow;
+    const int la = pl * ss + lpad(i);
+    cx<T> pre[NC];
+    auto load = [&](int t) {
+        const long long o = (long long)t * kThreads + threadIdx.x;
+        const bool in = o < nlast;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pre[c] = in ? S[c * g.nspec + o] : cx<T>{T(0), T(0)};
+    };
+    double esum = 0.0;
+    int t = blockIdx.x;
+    if (t < ntiles) load(t);
+    for (; t < ntiles; t += gridDim.x) {
+        // LDS addresses are recomputed per tile rather than kept in registers
+        // across the loop (which would cost the occupancy the pipeline needs)
+        int opq = 0;
+        asm volatile("" : "+s"(opq));
+        cx<T>* const A = A0 + opq;
+        cx<T>* const B = B0 + opq;
+        const cx<T>* const tw = tw0 + opq;
+        __syncthreads();  // the previous tile's stores have read A/B
+#pragma unroll
+        for (int c = 0; c < NC; ++c) A[c * np * ss + la] = pre[c];
+        __syncthreads();
+        const int tn = t + gridDim.x;
+        if (tn < ntiles) load(tn);  // next tile in flight during this one
+        cx<T>* R = lds_fft<T, -1>(A, B, pr, NC * np, ss, tw, threadIdx.x + opq);
+        const long long o = (long long)t * kThreads + threadIdx.x;
+        const bool in = o < nlast;
+        if (in) {
+            int kx, ky, kz;
+            gamma_freq(g, t * np + pl, i, kx, ky, kz);
+            esum += gamma_point<T, POL>(R, ss, np, pl, i, kx, ky, kz, g, lam0, mu0, alpha, beta, dc_mode, E,
+                                        dc_mean, st);
+        }
+        __syncthreads();
+        const cx<T>* Q = lds_fft<T, +1>(R, R == A ? B : A, pr, 6 * np, ss, tw, threadIdx.x + opq);
+        if (in) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) S[c * g.nspec + o] = Q[c * np * ss + la];
         }
     }
     double ev[1] = {esum};

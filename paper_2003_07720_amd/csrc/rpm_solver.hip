@@ -39,6 +39,14 @@ constexpr int kYPipeBlocks = RPM_YPIPE_BLOCKS;  // persistent grid of the pipeli
 #define RPM_TDOTS_BLOCKS 1024
 #endif
 constexpr int kTdotsBlocks = RPM_TDOTS_BLOCKS;  // grid cap of the basis products
+#ifndef RPM_GPIPE
+#define RPM_GPIPE 1
+#endif
+#ifndef RPM_GPIPE_BLOCKS
+#define RPM_GPIPE_BLOCKS 1280
+#endif
+constexpr bool kGPipe = RPM_GPIPE != 0;        // software-pipelined gamma pass
+constexpr int kGPipeBlocks = RPM_GPIPE_BLOCKS;  // its persistent grid
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -92,6 +100,8 @@ struct Shapes {
     Plan px, py, pr;
     size_t lds_x, lds_y, lds_g;
     int G1, Gy, Gyf, G3, Gg, Gp, Gq;  // Gyf: forward y-pass tiles (all spectral components)
+    int Gt;                           // gamma tiles
+    bool gpipe;                       // pipelined gamma pass (tiles of kThreads elements per component)
     bool ok;
 };
 
@@ -126,13 +136,16 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     // gamma pass: np pencils x ncomp components along the last axis
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
-    int np = 2;  // two pencils per gamma tile: more resident tiles per CU
+    // pipelined gamma pass: np pencils of exactly kThreads elements per component
+    int np = (kGPipe && kThreads % nrow == 0) ? kThreads / nrow : 2;
+    if ((size_t)(2 * ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) np = 2;
     while (np > 1 && (size_t)(2 * ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8 > (size_t)kLdsCap) --np;
     g.np = np;
     s.lds_g = (size_t)(2 * ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8;
     if (s.lds_x > (size_t)kLdsCap || s.lds_y > (size_t)kLdsCap || s.lds_g > (size_t)kLdsCap) s.ok = false;
     if (g.ty * g.nx > MV * kThreads) s.ok = false;
     g.fnx = make_fdiv(g.nx);
+    for (int a = 0; a < 3; ++a) g.kh[a] = 2.0 * 3.14159265358979323846 / (double)n[a];
     g.fny = make_fdiv(g.ny);
     g.fnh = make_fdiv(g.nh);
     g.fty = make_fdiv(g.ty);
@@ -144,7 +157,9 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     s.G1 = g.nz * (g.ny / g.ty);
     s.Gy = 6 * g.nh * (g.nz / g.tz);
     s.Gyf = ncomp * g.nh * (g.nz / g.tz);
-    s.G3 = (npen + g.np - 1) / g.np;
+    s.Gt = (npen + g.np - 1) / g.np;
+    s.gpipe = kGPipe && g.np * nrow == kThreads;
+    s.G3 = s.gpipe ? std::min(s.Gt, kGPipeBlocks) : s.Gt;  // gamma blocks (one error partial each)
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
     s.Gp = (int)((6 * g.N + kVecBlock - 1) / kVecBlock);
     const long long ntile = (6 * g.N + kZTile - 1) / kZTile;
@@ -404,14 +419,17 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         c.mark_end(RPM_K_YFWD, ev, 2.0 * (pol ? cf : 1.0) * specB);
     }
     c.mark_begin(RPM_K_GAMMA, ev);
-    if (pol)
-        k_gamma<T, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0,
-                                                             c.alpha, c.beta, dc_mode, Edev, pmean, sh.G1, perr,
-                                                             c.st, done);
-    else
-        k_gamma<T, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(g.two_d ? S1 : S2, g, sh.pr, c.twr(), c.lam0, c.mu0,
-                                                              c.alpha, c.beta, dc_mode, Edev, pmean, sh.G1, perr,
-                                                              c.st, done);
+    cx<T>* Sg = g.two_d ? S1 : S2;
+#define RPM_GAMMA_ARGS                                                                                    \
+    Sg, g, sh.pr, c.twr(), c.lam0, c.mu0, c.alpha, c.beta, dc_mode, Edev, pmean, sh.G1, perr, c.st
+    if (sh.gpipe) {
+        if (pol) k_gpipe<T, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
+        else k_gpipe<T, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
+    } else {
+        if (pol) k_gamma<T, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, done);
+        else k_gamma<T, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, done);
+    }
+#undef RPM_GAMMA_ARGS
     c.mark_end(RPM_K_GAMMA, ev, ((pol ? cf : 1.0) + 1.0) * specB);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
