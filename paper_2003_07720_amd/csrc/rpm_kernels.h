@@ -865,6 +865,12 @@ struct Raw4<double> {
     }
 };
 
+// Up to four field pointers of a product kernel (unused slots null).
+template <typename TA>
+struct Fields {
+    const TA* f[4];
+};
+
 // Column-group products (no update): wave g of a block of 64 * ceil(p / 8)
 // threads owns columns 8g .. 8g+7 and streams their slices of every tile the
 // block visits (tiles b, b + G, ...), so a wave keeps only 8 accumulators per
@@ -873,21 +879,19 @@ struct Raw4<double> {
 // as a wave-uniform base plus the lane offset.  Partial sums are
 // column-major: part[(f * ld + j) * G + b], G = gridDim.x.
 template <bool FULL, typename TA, typename TZ, int NF>
-__device__ __forceinline__ void gdots_tile(const TA* __restrict__ a0t, const TA* __restrict__ a1t,
-                                           const TZ* __restrict__ zt, int lo, int nj, long long e0, long long L6,
-                                           long long N3, double (&acc)[NF][8])
+__device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, const TZ* __restrict__ zt, int lo,
+                                           int nj, long long e0, long long L6, long long N3,
+                                           double (&acc)[NF][8])
 {
-    double w[4], f0[4], f1[4];
+    double w[4], fv[NF][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) w[u] = (FULL || e0 + u < L6) ? (e0 + u < N3 ? 1.0 : 2.0) : 0.0;
-    Raw4<TA> r0, r1;
+    Raw4<TA> ra[NF];
     Raw4<TZ> raw[8];
-    if (FULL) {
-        r0.load(a0t + lo);
-        if (NF > 1) r1.load(a1t + lo);
-    } else {
-        r0.load_tail(a0t + lo, e0, L6);
-        if (NF > 1) r1.load_tail(a1t + lo, e0, L6);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        if (FULL) ra[f].load(a.f[f] + t0 + lo);
+        else ra[f].load_tail(a.f[f] + t0 + lo, e0, L6);
     }
     // slots past the group's last column repeat it (valid memory); their sums
     // are never stored
@@ -897,30 +901,27 @@ __device__ __forceinline__ void gdots_tile(const TA* __restrict__ a0t, const TA*
         if (FULL) raw[u].load(zc + lo);
         else raw[u].load_tail(zc + lo, e0, L6);
     }
-    r0.get(f0);
-    if (NF > 1) r1.get(f1);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        f0[q] *= w[q];
-        if (NF > 1) f1[q] *= w[q];
+    for (int f = 0; f < NF; ++f) {
+        ra[f].get(fv[f]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fv[f][q] *= w[q];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         double z[4];
         raw[u].get(z);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            acc[0][u] += z[q] * f0[q];
-            if (NF > 1) acc[NF - 1][u] += z[q] * f1[q];
-        }
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) acc[f][u] += z[q] * fv[f][q];
     }
 }
 
 // SITE only separates the call sites in profiles (0: the per-step
 // projections, 1: basis growth); the code is the same.
 template <typename TA, typename TZ, int NF, int SITE>
-__global__ __launch_bounds__(512) void k_gdots(const TA* __restrict__ a0, const TA* __restrict__ a1,
-                                               const TZ* __restrict__ Z, int p, int zP, long long N,
+__global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restrict__ Z, int p, int zP, long long N,
                                                double* __restrict__ part, int ld)
 {
     const int lane = threadIdx.x & 63;
@@ -937,12 +938,11 @@ __global__ __launch_bounds__(512) void k_gdots(const TA* __restrict__ a0, const 
         for (int u = 0; u < 8; ++u) acc[f][u] = 0.0;
     long long tile = blockIdx.x;
     for (; tile < nfull; tile += gridDim.x)
-        gdots_tile<true, TA, TZ, NF>(a0 + tile * kZTile, a1 + tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile,
-                                     lo, nj, tile * kZTile + lo, L6, N3, acc);
+        gdots_tile<true, TA, TZ, NF>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+                                     tile * kZTile + lo, L6, N3, acc);
     if (tile == nfull && nfull * kZTile < L6)  // the last, partial tile
-        gdots_tile<false, TA, TZ, NF>(a0 + tile * kZTile, a1 + tile * kZTile,
-                                      Z + (tile * zP + j0) * (long long)kZTile, lo, nj, tile * kZTile + lo, L6, N3,
-                                      acc);
+        gdots_tile<false, TA, TZ, NF>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+                                      tile * kZTile + lo, L6, N3, acc);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -954,38 +954,39 @@ __global__ __launch_bounds__(512) void k_gdots(const TA* __restrict__ a0, const 
 
 // Update-and-project (Gram-Schmidt step) k_tdots: a wave owns whole tiles;
 // lane l holds elements 4l .. 4l+3 of its tile and all p columns of it, so
-// the update a_0 <- a_0 - sum_j coef_j Z_j (UPD, written back) is complete in
-// registers before the products
+// the update a_f <- a_f - sum_j coef[f * ld + j] Z_j (UPD, every field,
+// written back) is complete in registers before the products
 //   part[b * rs + f * ld + j] = sum_e w(e) Z_j[e] a_f[e]      (j < p, f < NF)
-// and, NRM, part[b * rs + NF * ld] = sum_e w(e) a_0[e]^2 (after the update).
-// PC bounds p at compile time (one FP64 accumulator per column in registers).
-// Block b takes tiles b * kWaves + wave + k * gridDim.x * kWaves.
+// and, NRM, the Gram entries of the fields after the update at
+// part[b * rs + NF * ld + m]: <a_0, a_0> (NF = 1), or <a_0, a_0>, <a_1, a_1>,
+// <a_0, a_1> (NF = 2).
+// PC bounds p at compile time (one FP64 accumulator per column and field in
+// registers).  Block b takes tiles b * kWaves + wave + k * gridDim.x * kWaves.
+template <int NF>
+constexpr int tdots_nrm() { return NF == 1 ? 1 : 3; }
 
 // One tile of k_tdots for one lane: elements e0 .. e0+3 (FULL: all inside the
 // vector, no guards).
 template <bool FULL, typename TA, typename TZ, int NF, int PC, bool UPD, bool NRM>
-__device__ __forceinline__ void tdots_tile(TA* __restrict__ a0, const TA* __restrict__ a1,
-                                           const TZ* __restrict__ zt, long long e0, long long L6, long long N3,
-                                           int p, const double* cf, double (&acc)[NF][PC], double& nrm)
+__device__ __forceinline__ void tdots_tile(TA* __restrict__ a0, TA* __restrict__ a1, const TZ* __restrict__ zt,
+                                           long long e0, long long L6, long long N3, int p,
+                                           const double (*cf)[PC], double (&acc)[NF][PC],
+                                           double (&nrm)[tdots_nrm<NF>()])
 {
     constexpr int CG = 8;  // columns whose loads are issued together
-    double w[4], f0[4], f1[4];
+    TA* const af[2] = {a0, a1};
+    double w[4], fv[NF][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) w[u] = (FULL || e0 + u < L6) ? (e0 + u < N3 ? 1.0 : 2.0) : 0.0;
-    if (FULL) {
-        Raw4<TA> r0;
-        r0.load(a0 + e0);
-        r0.get(f0);
-        if (NF > 1) {
-            Raw4<TA> r1;
-            r1.load(a1 + e0);
-            r1.get(f1);
-        }
-    } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            f0[u] = e0 + u < L6 ? (double)a0[e0 + u] : 0.0;
-            f1[u] = (NF > 1 && e0 + u < L6) ? (double)a1[e0 + u] : 0.0;
+    for (int f = 0; f < NF; ++f) {
+        if (FULL) {
+            Raw4<TA> r;
+            r.load(af[f] + e0);
+            r.get(fv[f]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) fv[f][u] = e0 + u < L6 ? (double)af[f][e0 + u] : 0.0;
         }
     }
     // columns past p in a load group are clamped to column p - 1 (valid memory)
@@ -1006,27 +1007,37 @@ __device__ __forceinline__ void tdots_tile(TA* __restrict__ a0, const TA* __rest
                 load_group(g, raw);
 #pragma unroll
                 for (int u = 0; u < CG; ++u) {
-                    const double c = cf[g * CG + u];  // zero past p
                     double z[4];
                     raw[u].get(z);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) f0[q] -= c * z[q];
+                    for (int f = 0; f < NF; ++f) {
+                        const double c = cf[f][g * CG + u];  // zero past p
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) fv[f][q] -= c * z[q];
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (FULL || e0 + q < L6) a0[e0 + q] = (TA)f0[q];
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (FULL || e0 + q < L6) af[f][e0 + q] = (TA)fv[f][q];
     }
     if (NRM) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) nrm += w[q] * f0[q] * f0[q];
+        for (int q = 0; q < 4; ++q) {
+            nrm[0] += w[q] * fv[0][q] * fv[0][q];
+            if constexpr (NF == 2) {
+                nrm[1] += w[q] * fv[1][q] * fv[1][q];
+                nrm[2] += w[q] * fv[0][q] * fv[1][q];
+            }
+        }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        f0[q] *= w[q];
-        if (NF > 1) f1[q] *= w[q];
-    }
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) fv[f][q] *= w[q];
 #pragma unroll
     for (int g = 0; g < PC / CG; ++g) {
         if (g * CG < p) {
@@ -1037,38 +1048,44 @@ __device__ __forceinline__ void tdots_tile(TA* __restrict__ a0, const TA* __rest
                 const double m = g * CG + u < p ? 1.0 : 0.0;
                 double z[4];
                 raw[u].get(z);
-                double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    s0 += z[q] * f0[q];
-                    if (NF > 1) s1 += z[q] * f1[q];
+                for (int f = 0; f < NF; ++f) {
+                    double sf = 0.0;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) sf += z[q] * fv[f][q];
+                    acc[f][g * CG + u] += m * sf;
                 }
-                acc[0][g * CG + u] += m * s0;
-                if (NF > 1) acc[NF - 1][g * CG + u] += m * s1;
             }
         }
     }
 }
 
 template <typename TA, typename TZ, int NF, int PC, bool UPD, bool NRM>
-__global__ __launch_bounds__(kThreads) void k_tdots(TA* __restrict__ a0, const TA* __restrict__ a1,
+__global__ __launch_bounds__(kThreads) void k_tdots(TA* __restrict__ a0, TA* __restrict__ a1,
                                                     const TZ* __restrict__ Z, int p, int zP,
                                                     const double* __restrict__ coef, long long N,
                                                     double* __restrict__ part, int ld, int rs)
 {
-    constexpr int NA = NF * PC + (NRM ? 1 : 0);
+    static_assert(NF == 1 || NF == 2, "one or two fields");
+    constexpr int NM = tdots_nrm<NF>();
+    constexpr int NA = NF * PC + (NRM ? NM : 0);
     static_assert(PC % 8 == 0, "column capacity is a multiple of the load group");
     __shared__ double red[kWaves][NA];
-    __shared__ double cf[UPD ? PC : 1];
+    __shared__ double cf[UPD ? NF : 1][PC];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (UPD) {
-        for (int j = threadIdx.x; j < PC; j += kThreads) cf[j] = j < p ? coef[j] : 0.0;
+        for (int i = threadIdx.x; i < NF * PC; i += kThreads) {
+            const int f = i / PC, j = i - f * PC;
+            cf[f][j] = j < p ? coef[f * ld + j] : 0.0;
+        }
         __syncthreads();
     }
     const long long L6 = 6 * N, N3 = 3 * N;
     const long long nfull = L6 / kZTile;
     double acc[NF][PC];
-    double nrm = 0.0;
+    double nrm[NM];
+#pragma unroll
+    for (int m = 0; m < NM; ++m) nrm[m] = 0.0;
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -1093,8 +1110,11 @@ __global__ __launch_bounds__(kThreads) void k_tdots(TA* __restrict__ a0, const T
             }
         }
     if (NRM) {
-        const double s = wave_sum(nrm);
-        if (lane == 0) red[wave][NF * PC] = s;
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+            const double s = wave_sum(nrm[m]);
+            if (lane == 0) red[wave][NF * PC + m] = s;
+        }
     }
     __syncthreads();
     double* out = part + (long long)blockIdx.x * rs;
@@ -1104,7 +1124,7 @@ __global__ __launch_bounds__(kThreads) void k_tdots(TA* __restrict__ a0, const T
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < kWaves; ++q) s += red[q][i];
-        out[f < NF ? f * ld + j : NF * ld] = s;
+        out[f < NF ? f * ld + j : NF * ld + (i - NF * PC)] = s;
     }
 }
 
@@ -1529,6 +1549,35 @@ __global__ void k_col_put(const TI* __restrict__ in, double scale, T* __restrict
         const T v = (T)((double)in[i] * scale);
         Z[zix(i, j, zP)] = v;
         if (copy) copy[i] = v;
+    }
+}
+
+// The new basis columns of a growth step from the two re-orthogonalised
+// candidates v0, v1 (FP64): z0 = s0 v0 and z1 = s1 (v1 - c01 z0), the second
+// made orthogonal to the first with c01 = <z0, v1>.  Each kept column goes to
+// Z (slots j0, j0 + 1; only z1 when the first is dropped, then at j0) and to
+// a contiguous copy (out0, out1) for its Jacobian-vector product.
+// keep: bit 0 first kept, bit 1 second kept.
+template <typename T>
+__global__ void k_col_put2(const double* __restrict__ v0, const double* __restrict__ v1, double s0, double c01,
+                           double s1, int keep, T* __restrict__ Z, int j0, int zP, T* __restrict__ out0,
+                           T* __restrict__ out1, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double z0 = 0.0;
+    int j = j0;
+    if (keep & 1) {
+        z0 = v0[i] * s0;
+        const T t = (T)z0;
+        Z[zix(i, j, zP)] = t;
+        out0[i] = t;
+        ++j;
+    }
+    if (keep & 2) {
+        const T t = (T)((v1[i] - c01 * z0) * s1);
+        Z[zix(i, j, zP)] = t;
+        out1[i] = t;
     }
 }
 

@@ -168,7 +168,7 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
 }
 
 struct Layout {
-    size_t st, twx, twy, twr, lame, hist, pmean, perr, pinc, pdots, pg, sums, gsum, ring[4], eps, tmp, tmp2, S1, S2,
+    size_t st, twx, twy, twr, lame, hist, pmean, perr, pinc, pdots, pg, sums, gsum, gx, ring[4], eps, tmp, tmp2, S1, S2,
         Z, W, D1, D0, shift, sub64, total;
     int ld;
     long long hist_cap;
@@ -222,10 +222,11 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.pinc = take(sizeof(double) * s.G1);
     L.pdots = take(sizeof(double) * 2 * L.ld * std::max(std::max(s.G1, s.Gp), s.Gq));
     const long long Gd = (6 * g.N + 4 * kThreads - 1) / (4 * kThreads);  // k_growth_diff blocks (3 partials each)
-    L.pg = take(sizeof(double) * std::max((size_t)(2 * kMaxP + 4) * std::max(std::max(s.Gg, s.Gp), s.Gq),
+    L.pg = take(sizeof(double) * std::max((size_t)(4 * kMaxP + 4) * std::max(std::max(s.Gg, s.Gp), s.Gq),
                                           (size_t)(3 * Gd)));
     L.sums = take(sizeof(double) * (2 * kMaxP + 8));
     L.gsum = take(sizeof(double) * (kMaxP + 8));
+    L.gx = take(sizeof(double) * (10 * kMaxP + 16));
     for (int i = 0; i < 4; ++i) L.ring[i] = take(fT);
     L.eps = take(fT);
     L.tmp = take(pmax > 0 ? fT : 0);
@@ -338,6 +339,7 @@ struct Ctx {
     T* Wb() { return at<T>(L.W); }  // tiled W = F_u Z
     double* sums() { return at<double>(L.sums); }
     double* gsum() { return at<double>(L.gsum); }
+    double* gx() { return at<double>(L.gx); }
     double* pdots() { return at<double>(L.pdots); }
     double* pg() { return at<double>(L.pg); }
 
@@ -455,27 +457,27 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
 // Products <Z_j, a_f> (j < p) with the tiled basis: column-major partials
 // part[(f * ld + j) * G + b], one wave per group of 8 columns.
 template <typename TA, typename TZ, int NF, int SITE>
-void launch_gdots(hipStream_t s, int G, const TA* a0, const TA* a1, const TZ* Z, int p, int zP, long long N,
-                  double* part, int ld)
+void launch_gdots(hipStream_t s, int G, Fields<TA> a, const TZ* Z, int p, int zP, long long N, double* part, int ld)
 {
     const int ng = (p + 7) / 8;
-    k_gdots<TA, TZ, NF, SITE><<<G, 64 * ng, 0, s>>>(a0, a1, Z, p, zP, N, part, ld);
+    k_gdots<TA, TZ, NF, SITE><<<G, 64 * ng, 0, s>>>(a, Z, p, zP, N, part, ld);
 }
 
-// v <- v - sum_j coef_j Z_j, then the products <Z_j, v> (and, NRM, <v, v>):
-// row-major partials part[b * rs + j], norm at part[b * rs + kMaxP].
-template <typename TZ, bool NRM>
-void launch_update(hipStream_t s, int G, double* v, const TZ* Z, int p, int zP, const double* coef, long long N,
-                   double* part, int rs)
+// v_f <- v_f - sum_j coef[f * kMaxP + j] Z_j (f < NF), then the products
+// <Z_j, v_f> (and, NRM, the Gram entries of the v_f): row-major partials
+// part[b * rs + f * kMaxP + j], Gram entries from part[b * rs + NF * kMaxP].
+template <typename TZ, int NF, bool NRM>
+void launch_update(hipStream_t s, int G, double* v0, double* v1, const TZ* Z, int p, int zP, const double* coef,
+                   long long N, double* part, int rs)
 {
     if (p <= 8)
-        k_tdots<double, TZ, 1, 8, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
+        k_tdots<double, TZ, NF, 8, true, NRM><<<G, kThreads, 0, s>>>(v0, v1, Z, p, zP, coef, N, part, kMaxP, rs);
     else if (p <= 16)
-        k_tdots<double, TZ, 1, 16, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
+        k_tdots<double, TZ, NF, 16, true, NRM><<<G, kThreads, 0, s>>>(v0, v1, Z, p, zP, coef, N, part, kMaxP, rs);
     else if (p <= 32)
-        k_tdots<double, TZ, 1, 32, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
-    else
-        k_tdots<double, TZ, 1, 64, true, NRM><<<G, kThreads, 0, s>>>(v, nullptr, Z, p, zP, coef, N, part, kMaxP, rs);
+        k_tdots<double, TZ, NF, 32, true, NRM><<<G, kThreads, 0, s>>>(v0, v1, Z, p, zP, coef, N, part, kMaxP, rs);
+    else if constexpr (NF == 1)
+        k_tdots<double, TZ, 1, 64, true, NRM><<<G, kThreads, 0, s>>>(v0, v1, Z, p, zP, coef, N, part, kMaxP, rs);
 }
 
 // zeta_j = <Z_j, xi> (and, direct, z_j = <Z_j, eps>) partial sums for the Newton step.
@@ -486,9 +488,10 @@ void project(Ctx<T>& c, const T* xi, const T* eps, int p, bool direct)
     hipEvent_t ev;
     c.mark_begin(RPM_K_PROJECT, ev);
     if (direct)
-        launch_gdots<T, T, 2, 0>(c.s, c.sh.Gq, xi, eps, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+        launch_gdots<T, T, 2, 0>(c.s, c.sh.Gq, Fields<T>{{xi, eps}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(),
+                                 c.L.ld);
     else
-        launch_gdots<T, T, 1, 0>(c.s, c.sh.Gq, xi, nullptr, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+        launch_gdots<T, T, 1, 0>(c.s, c.sh.Gq, Fields<T>{{xi}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
     c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * ((direct ? 2 : 1) + p));
 }
 
@@ -594,6 +597,95 @@ void project_compatible(Ctx<T>& c, T* v, T* out)
     run_F<T>(c, v, 0, nullptr, v, out, OUT_T, 1, DC_ZERO, c.st->Ezero, nullptr);
 }
 
+// Adds NV (1 or 2) candidate columns v (FP64, overwritten) to the basis:
+// two classical Gram-Schmidt passes against Z for both at once (coefficients;
+// the update fused with the second coefficients; the second update fused with
+// the Gram entries of the results), then the second made orthogonal to the
+// first and both normalised as they are stored; a candidate whose norm after
+// the projections is not above 1e-10 is dropped.  One Jacobian-vector
+// product per kept column, then the new columns of H and of the Gram matrix
+// in one pass over Z and the new rows of H in one pass over W.  NV = 2 needs
+// p <= 32 and two free slots.  Returns the number of columns added, -1 on a
+// HIP error.
+template <typename T, int NV>
+int add_columns(Ctx<T>& c, int& p, double* const* v, int* jvps)
+{
+    const long long N = c.sh.g.N;
+    const long long nel = 6 * N;
+    const int gb = (int)((nel + 255) / 256);
+    const int Gq = c.sh.Gq;
+    const int rs = 2 * kMaxP + 3;
+    constexpr int NM = NV == 1 ? 1 : 3;
+    T* tmp = c.template at<T>(c.L.tmp);
+    T* tmp2 = c.template at<T>(c.L.tmp2);
+    // the candidates' FP64 storage is free once the columns are stored: it
+    // takes the Jacobian-vector products
+    T* wout[2] = {reinterpret_cast<T*>(c.template at<double>(c.L.D1)),
+                  reinterpret_cast<T*>(c.template at<double>(c.L.D0))};
+    double* X = c.gx();
+    double* C1 = X;                      // NV x kMaxP
+    double* C2 = X + 2 * kMaxP;          // NV x kMaxP
+    double* nr = X + 4 * kMaxP;          // Gram entries of the projected candidates
+    double* HZ = X + 4 * kMaxP + 4;      // per new column: H column, Gram column (kMaxP + 2 each)
+    double* RW = HZ + 4 * (kMaxP + 2);   // per new column: H row
+    double* v1 = NV == 2 ? v[1] : nullptr;
+    Fields<double> fv{{v[0], v1}};
+    if (p > 0) {
+        launch_gdots<double, T, NV, 1>(c.s, Gq, fv, c.Zb(), p, c.pmax, N, c.pg(), kMaxP);
+        for (int f = 0; f < NV; ++f) reduce_cols(c, c.pg() + (long long)f * kMaxP * Gq, Gq, 1, Gq, p, C1 + f * kMaxP);
+        launch_update<T, NV, false>(c.s, Gq, v[0], v1, c.Zb(), p, c.pmax, C1, N, c.pg(), rs);
+        for (int f = 0; f < NV; ++f) reduce_cols(c, c.pg() + f * kMaxP, Gq, rs, 1, p, C2 + f * kMaxP);
+    }
+    launch_update<T, NV, true>(c.s, Gq, v[0], v1, c.Zb(), p, c.pmax, C2, N, c.pg(), rs);
+    reduce_cols(c, c.pg() + NV * kMaxP, Gq, rs, 1, NM, nr);
+    double g[3] = {0.0, 0.0, 0.0};
+    if (!sync_read(c, g, nr, sizeof(double) * NM)) return -1;
+    const double vn0 = std::sqrt(std::max(g[0], 0.0));
+    const bool keep0 = vn0 > 1e-10;
+    double c01 = 0.0, vn1 = 0.0;
+    bool keep1 = false;
+    if (NV == 2) {
+        // |v1 - <z0, v1> z0|^2 = |v1|^2 - <z0, v1>^2 with z0 = v0 / |v0|
+        c01 = keep0 ? g[2] / vn0 : 0.0;
+        vn1 = std::sqrt(std::max(g[1] - c01 * c01, 0.0));
+        keep1 = vn1 > 1e-10;
+    }
+    const int nacc = (keep0 ? 1 : 0) + (keep1 ? 1 : 0);
+    if (nacc == 0) return 0;
+    T* zc[2] = {tmp, tmp2};
+    k_col_put2<T><<<gb, 256, 0, c.s>>>(v[0], v1, keep0 ? 1.0 / vn0 : 0.0, c01, keep1 ? 1.0 / vn1 : 0.0,
+                                       (keep0 ? 1 : 0) | (keep1 ? 2 : 0), c.Zb(), p, c.pmax, tmp,
+                                       keep0 ? tmp2 : tmp, nel);
+    // Jacobian-vector products w = F(z; E = 0)
+    for (int a = 0; a < nacc; ++a) {
+        run_F<T>(c, zc[a], 0, nullptr, zc[a], wout[a], OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
+        k_col_put<T, T><<<gb, 256, 0, c.s>>>(wout[a], 1.0, c.Wb(), p + a, c.pmax, nullptr, nel);
+        ++*jvps;
+    }
+    // H columns <z_i, w_a> and Gram columns <z_i, z_a>, i <= p + a, in one pass
+    const int ld = kMaxP + 2;
+    if (nacc == 1)
+        launch_gdots<T, T, 2, 1>(c.s, Gq, Fields<T>{{wout[0], zc[0]}}, c.Zb(), p + 1, c.pmax, N, c.pg(), kMaxP);
+    else
+        launch_gdots<T, T, 4, 1>(c.s, Gq, Fields<T>{{wout[0], zc[0], wout[1], zc[1]}}, c.Zb(), p + 2, c.pmax, N,
+                                 c.pg(), kMaxP);
+    for (int f = 0; f < 2 * nacc; ++f)
+        reduce_cols(c, c.pg() + (long long)f * kMaxP * Gq, Gq, 1, Gq, p + f / 2 + 1, HZ + f * ld);
+    // H rows <z_a, w_j>, j < p + a, in one pass over W
+    if (p + nacc - 1 > 0) {
+        if (nacc == 1)
+            launch_gdots<T, T, 1, 1>(c.s, Gq, Fields<T>{{zc[0]}}, c.Wb(), p, c.pmax, N, c.pg(), kMaxP);
+        else
+            launch_gdots<T, T, 2, 1>(c.s, Gq, Fields<T>{{zc[0], zc[1]}}, c.Wb(), p + 1, c.pmax, N, c.pg(), kMaxP);
+        for (int a = 0; a < nacc; ++a)
+            if (p + a > 0) reduce_cols(c, c.pg() + (long long)a * kMaxP * Gq, Gq, 1, Gq, p + a, RW + a * kMaxP);
+    }
+    for (int a = 0; a < nacc; ++a) k_border<<<1, 1, 0, c.s>>>(c.st, HZ + 2 * a * ld, RW + a * kMaxP,
+                                                              HZ + (2 * a + 1) * ld, p + a);
+    p += nacc;
+    return nacc;
+}
+
 // Basis growth In(q, Z) after main-loop F application number it (Sec. 3:
 // QR of the last two differences of q, one or two columns, H bordered by one
 // JVP per column).  Returns the number of columns added, or -1 on HIP error.
@@ -634,15 +726,16 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     }
     if (o->replay && growth_index < o->replay_len) want = o->replay[growth_index];
     *want_out = want;
-    int added = 0;
-    for (int col = 0; col < want && p < c.pmax; ++col) {
+    // candidates: the normalised differences, projected onto zero-mean
+    // compatible fields (Lippmann-Schwinger map) and back in FP64
+    const long long nel = 6 * N;
+    const int gb = (int)((nel + 255) / 256);
+    double* cand[2];
+    int nc = 0;
+    for (int col = 0; col < want && col < 2; ++col) {
         double* v = col == 0 ? D1 : D0;
         const double nrm = col == 0 ? T11 : T22;
-        if (!(nrm > 0.0)) continue;
-        if (col == 1 && !two) continue;
-        // normalise, project onto zero-mean compatible fields (Lippmann-Schwinger map), back to FP64
-        const long long nel = 6 * N;
-        const int gb = (int)((nel + 255) / 256);
+        if (!(nrm > 0.0) || (col == 1 && !two)) continue;
         k_convert<double, T><<<gb, 256, 0, c.s>>>(v, tmp, 1.0 / nrm, nel);
         if (c.pol) {
             // polarization iterates are not compatible: the differences stay as they are
@@ -651,45 +744,19 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
             project_compatible<T>(c, tmp, tmp2);
             k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
         }
-        // two classical Gram-Schmidt passes against Z: coefficients; the update fused
-        // with the second coefficients; the second update fused with the norm
-        const int Gq = c.sh.Gq;
-        const int rs = 2 * kMaxP + 1;
-        double* coef = c.gsum();
-        double* coef2 = c.sums() + kMaxP + 2;
-        if (p > 0) {
-            launch_gdots<double, T, 1, 1>(c.s, Gq, v, nullptr, c.Zb(), p, c.pmax, N, c.pg(), kMaxP);
-            reduce_cols(c, c.pg(), Gq, 1, Gq, p, coef);
-            launch_update<T, false>(c.s, Gq, v, c.Zb(), p, c.pmax, coef, N, c.pg(), rs);
-            reduce_cols(c, c.pg(), Gq, rs, 1, p, coef2);
+        cand[nc++] = v;
+    }
+    int added = 0;
+    if (nc == 2 && p + 2 <= c.pmax && p <= 32) {
+        const int r = add_columns<T, 2>(c, p, cand, jvps);
+        if (r < 0) return -1;
+        added += r;
+    } else {
+        for (int k = 0; k < nc && p < c.pmax; ++k) {
+            const int r = add_columns<T, 1>(c, p, cand + k, jvps);
+            if (r < 0) return -1;
+            added += r;
         }
-        launch_update<T, true>(c.s, Gq, v, c.Zb(), p, c.pmax, coef2, N, c.pg(), rs);
-        reduce_cols(c, c.pg() + kMaxP, Gq, rs, 1, 1, coef + kMaxP);
-        double n2;
-        if (!sync_read(c, &n2, coef + kMaxP, sizeof(n2))) return -1;
-        const double vn = std::sqrt(std::max(n2, 0.0));
-        if (!(vn > 1e-10)) continue;
-        // store z_p in the basis and keep a contiguous copy (tmp) for the map
-        k_col_put<double, T><<<gb, 256, 0, c.s>>>(v, 1.0 / vn, c.Zb(), p, c.pmax, tmp, nel);
-        // Jacobian-vector product w = F(z_p; E = 0)
-        run_F<T>(c, tmp, 0, nullptr, tmp, tmp2, OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
-        k_col_put<T, T><<<gb, 256, 0, c.s>>>(tmp2, 1.0, c.Wb(), p, c.pmax, nullptr, nel);
-        // column p of H, <z_i, w> (i <= p), and of the Gram matrix, <z_i, z_p>, in one pass
-        double* hcol = c.sums() + 1;
-        double* gram = c.sums() + kMaxP + 2;
-        launch_gdots<T, T, 2, 1>(c.s, Gq, tmp2, tmp, c.Zb(), p + 1, c.pmax, N, c.pg(), kMaxP);
-        reduce_cols(c, c.pg(), Gq, 1, Gq, p + 1, hcol);
-        reduce_cols(c, c.pg() + (long long)kMaxP * Gq, Gq, 1, Gq, p + 1, gram);
-        // new row: <z_p, w_j> for j < p
-        double* row = c.gsum();
-        if (p > 0) {
-            launch_gdots<T, T, 1, 1>(c.s, Gq, tmp, nullptr, c.Wb(), p, c.pmax, N, c.pg(), kMaxP);
-            reduce_cols(c, c.pg(), Gq, 1, Gq, p, row);
-        }
-        k_border<<<1, 1, 0, c.s>>>(c.st, hcol, row, gram, p);
-        ++p;
-        ++added;
-        ++*jvps;
     }
     if (added > 0) k_factor<<<1, 64, 0, c.s>>>(c.st, p);
     c.mark_end(RPM_K_GROWTH, ev);
