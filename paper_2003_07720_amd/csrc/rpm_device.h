@@ -190,14 +190,14 @@ __host__ __device__ constexpr int lrow(int n) { return n + (n >> 5) + 1; }
 // One Stockham stage over nseq sequences of length n held in LDS with row
 // stride ss.  Ns = product of the radices already applied.
 // tw[e] = exp(-2 pi i e / n), e in [0, n).
-template <typename T, int R, int D>
+template <typename T, int R, int D, int NT = kThreads>
 __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int n, int Ns,
                                           int nseq, int ss, const cx<T>* __restrict__ tw)
 {
     const int nb = n / R;
     const int total = nb * nseq;
     const int tws = n / (Ns * R);
-    for (int g = threadIdx.x; g < total; g += kThreads) {
+    for (int g = threadIdx.x; g < total; g += NT) {
         const int s = g / nb;
         const int j = g - s * nb;
         const cx<T>* in = src + s * ss;
@@ -223,14 +223,14 @@ __device__ __forceinline__ void fft_stage(const cx<T>* __restrict__ src, cx<T>* 
 
 // The same stage with the length and the stage position fixed at compile time
 // (power-of-two lengths): index arithmetic reduces to shifts and masks.
-template <typename T, int R, int D, int N, int NS>
+template <typename T, int R, int D, int N, int NS, int NT>
 __device__ __forceinline__ void fft_stage_ct(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, int nseq,
                                              int ss, const cx<T>* __restrict__ tw, int tid)
 {
     constexpr int nb = N / R;
     constexpr int tws = N / (NS * R);
     const int total = nb * nseq;
-    for (int g = tid; g < total; g += kThreads) {
+    for (int g = tid; g < total; g += NT) {
         const int s = g / nb;
         const int j = g & (nb - 1);
         const cx<T>* in = src + s * ss;
@@ -260,37 +260,37 @@ constexpr int ct_log2(int n) { return n <= 1 ? 0 : 1 + ct_log2(n / 2); }
 constexpr int ct_nst(int n) { return ct_log2(n) / 4 + (ct_log2(n) % 4 ? 1 : 0); }
 constexpr int ct_rad(int n, int st) { return st < ct_log2(n) / 4 ? 16 : (1 << (ct_log2(n) % 4)); }
 
-template <typename T, int D, int N, int ST, int NS>
+template <typename T, int D, int N, int ST, int NS, int NT>
 __device__ __forceinline__ cx<T>* ct_stages(cx<T>* src, cx<T>* dst, int nseq, int ss, const cx<T>* tw, int tid)
 {
     if constexpr (ST == ct_nst(N)) {
         return src;
     } else {
         constexpr int R = ct_rad(N, ST);
-        fft_stage_ct<T, R, D, N, NS>(src, dst, nseq, ss, tw, tid);
+        fft_stage_ct<T, R, D, N, NS, NT>(src, dst, nseq, ss, tw, tid);
         __syncthreads();
-        return ct_stages<T, D, N, ST + 1, NS * R>(dst, src, nseq, ss, tw, tid);
+        return ct_stages<T, D, N, ST + 1, NS * R, NT>(dst, src, nseq, ss, tw, tid);
     }
 }
 
 // Full LDS FFT of nseq sequences (data in a; b is the ping-pong buffer).
 // Caller must __syncthreads() after filling a.  Returns the buffer that holds
 // the natural-order result; all threads are synchronised on return.
-template <typename T, int D>
+template <typename T, int D, int NT = kThreads>
 __device__ cx<T>* lds_fft(cx<T>* a, cx<T>* b, const Plan& pl, int nseq, int ss, const cx<T>* tw,
                          int tid = threadIdx.x)
 {
-    if (pl.n == 128) return ct_stages<T, D, 128, 0, 1>(a, b, nseq, ss, tw, tid);
+    if (pl.n == 128) return ct_stages<T, D, 128, 0, 1, NT>(a, b, nseq, ss, tw, tid);
     int Ns = 1;
     cx<T>* src = a;
     cx<T>* dst = b;
     for (int st = 0; st < pl.nst; ++st) {
         const int R = pl.rad[st];
-        if (R == 16) fft_stage<T, 16, D>(src, dst, pl.n, Ns, nseq, ss, tw);
-        else if (R == 8) fft_stage<T, 8, D>(src, dst, pl.n, Ns, nseq, ss, tw);
-        else if (R == 4) fft_stage<T, 4, D>(src, dst, pl.n, Ns, nseq, ss, tw);
-        else if (R == 2) fft_stage<T, 2, D>(src, dst, pl.n, Ns, nseq, ss, tw);
-        else fft_stage<T, 3, D>(src, dst, pl.n, Ns, nseq, ss, tw);
+        if (R == 16) fft_stage<T, 16, D, NT>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else if (R == 8) fft_stage<T, 8, D, NT>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else if (R == 4) fft_stage<T, 4, D, NT>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else if (R == 2) fft_stage<T, 2, D, NT>(src, dst, pl.n, Ns, nseq, ss, tw);
+        else fft_stage<T, 3, D, NT>(src, dst, pl.n, Ns, nseq, ss, tw);
         __syncthreads();
         Ns *= R;
         cx<T>* t = src;
@@ -310,11 +310,12 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Sums M per-thread values over the workgroup; thread m < M writes the m-th
-// total to dst[m].  lds needs kWaves * M doubles.
-template <int M>
+// Sums M per-thread values over the workgroup of NT threads; thread m < M
+// writes the m-th total to dst[m].  lds needs (NT / 64) * M doubles.
+template <int M, int NT = kThreads>
 __device__ __forceinline__ void wg_sum_store(double (&v)[M], double* __restrict__ dst, double* lds)
 {
+    constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -326,7 +327,7 @@ __device__ __forceinline__ void wg_sum_store(double (&v)[M], double* __restrict_
     if (threadIdx.x < M) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) s += lds[w * M + threadIdx.x];
+        for (int w = 0; w < NW; ++w) s += lds[w * M + threadIdx.x];
         dst[threadIdx.x] = s;
     }
     __syncthreads();

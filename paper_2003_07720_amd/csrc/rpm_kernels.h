@@ -42,6 +42,7 @@ struct Geo {
 // element e of column j sits at zix(e, j, P).  Per-voxel recombination and the
 // basis products then read contiguous kilobyte slices.
 constexpr int kZTile = 256;
+constexpr int kMaxTy = 128;  // x-pass tiles hold at most this many rows
 __host__ __device__ __forceinline__ long long zix(long long e, int j, int P)
 {
     return ((e / kZTile) * (long long)P + j) * kZTile + (e % kZTile);
@@ -105,8 +106,8 @@ struct MaxV<double> { static constexpr int v = 4; };
 // too (components 6..11 of S1), for the polarization iteration.
 // grid: nz * (ny / ty) blocks.  LDS: 2 * ty * lrow(nx) + nx complex + reduction.
 // ---------------------------------------------------------------------------
-template <typename T, bool VEC, bool POL>
-__global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, const uint8_t* __restrict__ phase,
+template <typename T, bool VEC, bool POL, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_xfwd(const T* __restrict__ xin, const uint8_t* __restrict__ phase,
                                                    const double* __restrict__ lame, int use_ref, double lam0,
                                                    double mu0, cx<T>* __restrict__ S1,
                                                    double* __restrict__ part_mean, Geo g, Plan px,
@@ -114,7 +115,7 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MV = MaxV<T>::v;
+    constexpr int MV = MaxV<T>::v * kThreads / NT;  // voxels per thread
     const int nx = g.nx, ty = g.ty, ss = lrow(nx);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
@@ -128,93 +129,94 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
     const int nvox = ty * nx;
     const long long N = g.N;
 
-    for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
+    for (int i = threadIdx.x; i < nx; i += NT) tw[i] = twx[i];
 
-    // VEC: each thread takes runs of VL consecutive voxels (16-byte accesses)
+    // VEC: each thread takes runs of VL consecutive voxels (16-byte accesses).
+    // All strain loads are issued up front, the three components of the first
+    // transform's inputs first: the later components are only needed by the
+    // later transforms and stay in flight meanwhile.
     constexpr int VL = VEC ? (int)(16 / sizeof(T)) : 1;
+    constexpr int NI = MV / VL;
     using V = typename Vec4<T>::type;
-    T sig[MV][6];
-    T ev[POL ? MV : 1][6];
-    double msum[6] = {0, 0, 0, 0, 0, 0};
+    T e[MV][6];
+    T lamv[MV], muv[MV];
+    auto load_comp = [&](int c) {
 #pragma unroll
-    for (int i = 0; i < MV / VL; ++i) {
-        const int v0 = (threadIdx.x + i * kThreads) * VL;
-        if (v0 < nvox) {
+        for (int i = 0; i < NI; ++i) {
+            const int v0 = (threadIdx.x + i * NT) * VL;
             const long long gi = base + v0;
-            T e[VL][6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) {
+            if (v0 < nvox) {
                 if constexpr (VEC) {
                     const V t = *reinterpret_cast<const V*>(xin + c * N + gi);
                     const T* ts = reinterpret_cast<const T*>(&t);
 #pragma unroll
-                    for (int u = 0; u < VL; ++u) e[u][c] = ts[u];
+                    for (int u = 0; u < VL; ++u) e[i * VL + u][c] = ts[u];
                 } else {
-                    e[0][c] = xin[c * N + gi];
+                    e[i][c] = xin[c * N + gi];
                 }
+            } else {
+#pragma unroll
+                for (int u = 0; u < VL; ++u) e[i * VL + u][c] = T(0);
             }
+        }
+    };
 #pragma unroll
-            for (int u = 0; u < VL; ++u) {
+    for (int c = 0; c < 3; ++c) load_comp(c);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) msum[c] += (double)e[u][c];
-                T lam, mu;
-                if (use_ref) {
-                    lam = (T)lam0;
-                    mu = (T)mu0;
-                } else {
-                    const int ph = phase[gi + u];
-                    lam = (T)lame[2 * ph];
-                    mu = (T)lame[2 * ph + 1];
-                }
-                const T ltr = lam * (e[u][0] + e[u][1] + e[u][2]);
-                const T m2 = mu + mu;
+    for (int i = 0; i < NI; ++i) {
+        const int v0 = (threadIdx.x + i * NT) * VL;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    sig[i * VL + u][c] = m2 * e[u][c] + (c < 3 ? ltr : T(0));
-                    if constexpr (POL) ev[i * VL + u][c] = e[u][c];
-                }
+        for (int u = 0; u < VL; ++u) {
+            if (use_ref || v0 >= nvox) {
+                lamv[i * VL + u] = (T)lam0;
+                muv[i * VL + u] = (T)mu0;
+            } else {
+                const int ph = phase[base + v0 + u];
+                lamv[i * VL + u] = (T)lame[2 * ph];
+                muv[i * VL + u] = (T)lame[2 * ph + 1];
             }
-        } else {
-#pragma unroll
-            for (int u = 0; u < VL; ++u)
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    sig[i * VL + u][c] = T(0);
-                    if constexpr (POL) ev[i * VL + u][c] = T(0);
-                }
         }
     }
-    if (part_mean) wg_sum_store<6>(msum, part_mean + (long long)blockIdx.x * 6, red);
+#pragma unroll
+    for (int c = 3; c < 6; ++c) load_comp(c);
 
+    // sigma = C(x):eps of components 2q, 2q+1 (the trace term on the normal ones)
+    auto sig = [&](int v, int c) -> T {
+        const T s = (muv[v] + muv[v]) * e[v][c];
+        return c < 3 ? s + lamv[v] * (e[v][0] + e[v][1] + e[v][2]) : s;
+    };
+    double msum[6] = {0, 0, 0, 0, 0, 0};
     const int nh = g.nh;
 #pragma unroll
     for (int q = 0; q < (POL ? 6 : 3); ++q) {  // unrolled: the register arrays take constant indices
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < MV / VL; ++i) {
-            const int v0 = (threadIdx.x + i * kThreads) * VL;
+        for (int i = 0; i < NI; ++i) {
+            const int v0 = (threadIdx.x + i * NT) * VL;
             if (v0 < nvox) {
                 const int r = g.fnx.div(v0);
                 const int x = v0 - r * nx;
 #pragma unroll
                 for (int u = 0; u < VL; ++u) {
+                    const int v = i * VL + u;
                     cx<T> val;
-                    if constexpr (POL) {
-                        val = q < 3 ? cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]}
-                                    : cx<T>{ev[i * VL + u][2 * q - 6], ev[i * VL + u][2 * q - 5]};
+                    if (q < 3) {
+                        val = cx<T>{sig(v, 2 * q), sig(v, 2 * q + 1)};
+                        msum[2 * q] += (double)e[v][2 * q];
+                        msum[2 * q + 1] += (double)e[v][2 * q + 1];
                     } else {
-                        val = cx<T>{sig[i * VL + u][2 * q], sig[i * VL + u][2 * q + 1]};
+                        val = cx<T>{e[v][2 * q - 6], e[v][2 * q - 5]};
                     }
                     A[r * ss + lpad(x + u)] = val;
                 }
             }
         }
         __syncthreads();
-        const cx<T>* R = lds_fft<T, -1>(A, B, px, ty, ss, tw);
+        const cx<T>* R = lds_fft<T, -1, NT>(A, B, px, ty, ss, tw);
         // split the packed transform into the two real-input spectra
         cx<T>* outa = S1 + (long long)(2 * q) * g.nspec;
         cx<T>* outb = S1 + (long long)(2 * q + 1) * g.nspec;
-        for (int t = threadIdx.x; t < nh * ty; t += kThreads) {
+        for (int t = threadIdx.x; t < nh * ty; t += NT) {
             const int k = g.fty.div(t);
             const int r = t - k * ty;
             const cx<T> X = R[r * ss + lpad(k)];
@@ -225,6 +227,10 @@ __global__ __launch_bounds__(kThreads) void k_xfwd(const T* __restrict__ xin, co
             outa[o] = cx<T>{T(0.5) * s.x, T(0.5) * s.y};
             outb[o] = cx<T>{T(0.5) * d.y, T(-0.5) * d.x};
         }
+    }
+    if (part_mean) {
+        __syncthreads();
+        wg_sum_store<6, NT>(msum, part_mean + (long long)blockIdx.x * 6, red);
     }
 }
 
@@ -688,8 +694,8 @@ __global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g
 // are back.
 // grid: nz * (ny / ty).
 // ---------------------------------------------------------------------------
-template <typename T, bool POL>
-__global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
+template <typename T, bool POL, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
                                                    T* __restrict__ out, int out_mode, const T* __restrict__ shift,
                                                    double* __restrict__ part_inc, Geo g, Plan px,
                                                    const cx<T>* __restrict__ twx, const uint8_t* __restrict__ phase,
@@ -698,7 +704,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
 {
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
-    constexpr int MV = MaxV<T>::v;
+    constexpr int MV = MaxV<T>::v * kThreads / NT;  // voxels per thread
     const int nx = g.nx, ty = g.ty, ss = lrow(nx), nh = g.nh;
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
@@ -711,34 +717,71 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
     const long long N = g.N;
     const T invN = T(1.0 / (double)N);
 
-    for (int i = threadIdx.x; i < nx; i += kThreads) tw[i] = twx[i];
+    for (int i = threadIdx.x; i < nx; i += NT) tw[i] = twx[i];
     double inc = 0.0;  // sum of w (out - eps)^2 over the tile (correction solves)
     T tb[POL ? MV : 1][6];  // POL: t of this thread's voxels, all components
+    // Software pipeline over the three packed transforms: the spectra of the
+    // next pair and the strains of the current pair are loaded while the
+    // current pair is transformed.  KS bounds nh * ty / NT.
+    constexpr int KS = (MV * NT / 2 + kMaxTy + NT - 1) / NT;
+    const int nspt = nh * ty;
+    cx<T> pa[KS], pb[KS];
+    auto load_spec = [&](int q) {
+        const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
+        const cx<T>* inb = S1 + (long long)(2 * q + 1) * g.nspec;
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int t = threadIdx.x + u * NT;
+            if (t < nspt) {
+                const int k = g.fty.div(t);
+                const int r = t - k * ty;
+                const long long o = ((long long)k * g.nz + z) * g.ny + y0 + r;
+                pa[u] = ina[o];
+                pb[u] = inb[o];
+            }
+        }
+    };
+    load_spec(0);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         __syncthreads();
-        const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
-        const cx<T>* inb = S1 + (long long)(2 * q + 1) * g.nspec;
-        for (int t = threadIdx.x; t < nh * ty; t += kThreads) {
-            const int k = g.fty.div(t);
-            const int r = t - k * ty;
-            const long long o = ((long long)k * g.nz + z) * g.ny + y0 + r;
-            cx<T> a = ina[o];
-            cx<T> b = inb[o];
-            const bool selfc = (k == 0) || (2 * k == nx);
-            if (selfc) {
-                a.y = T(0);
-                b.y = T(0);
+#pragma unroll
+        for (int u = 0; u < KS; ++u) {
+            const int t = threadIdx.x + u * NT;
+            if (t < nspt) {
+                const int k = g.fty.div(t);
+                const int r = t - k * ty;
+                cx<T> a = pa[u];
+                cx<T> b = pb[u];
+                const bool selfc = (k == 0) || (2 * k == nx);
+                if (selfc) {
+                    a.y = T(0);
+                    b.y = T(0);
+                }
+                A[r * ss + lpad(k)] = cx<T>{a.x - b.y, a.y + b.x};
+                if (!selfc) A[r * ss + lpad(nx - k)] = cx<T>{a.x + b.y, b.x - a.y};
             }
-            A[r * ss + lpad(k)] = cx<T>{a.x - b.y, a.y + b.x};
-            if (!selfc) A[r * ss + lpad(nx - k)] = cx<T>{a.x + b.y, b.x - a.y};
         }
         __syncthreads();
-        const cx<T>* R = lds_fft<T, +1>(A, B, px, ty, ss, tw);
+        if (q < 2) load_spec(q + 1);
         const int ca = 2 * q, cb = 2 * q + 1;
+        T ea[POL ? 1 : MV], eb[POL ? 1 : MV];
+        if constexpr (!POL) {
+            if (out_mode == OUT_XI) {
+#pragma unroll
+                for (int i = 0; i < MV; ++i) {
+                    const int v = threadIdx.x + i * NT;
+                    if (v < nvox) {
+                        ea[i] = eps[ca * N + base + v];
+                        eb[i] = eps[cb * N + base + v];
+                    }
+                }
+            }
+        }
+        const cx<T>* R = lds_fft<T, +1, NT>(A, B, px, ty, ss, tw);
 #pragma unroll
         for (int i = 0; i < MV; ++i) {
-            const int v = threadIdx.x + i * kThreads;
+            const int v = threadIdx.x + i * NT;
             if (v < nvox) {
                 const int r = g.fnx.div(v);
                 const int x = v - r * nx;
@@ -749,8 +792,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                     tb[i][2 * q] = ta;
                     tb[i][2 * q + 1] = tb_;
                 } else if (out_mode == OUT_XI) {
-                    const T ea = eps[ca * N + gi], eb = eps[cb * N + gi];
-                    T oa = ea - ta, ob = eb - tb_;
+                    T oa = ea[i] - ta, ob = eb[i] - tb_;
                     if (shift) {
                         oa += shift[ca * N + gi];
                         ob += shift[cb * N + gi];
@@ -758,7 +800,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
                     out[ca * N + gi] = oa;
                     out[cb * N + gi] = ob;
                     if (part_inc) {
-                        const double da = (double)oa - (double)ea, db = (double)ob - (double)eb;
+                        const double da = (double)oa - (double)ea[i], db = (double)ob - (double)eb[i];
                         inc += frob_w(ca) * da * da + frob_w(cb) * db * db;
                     }
                 } else {
@@ -772,7 +814,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
         const T l0 = (T)lam0, m0 = (T)mu0, omb = (T)(1.0 - beta);
 #pragma unroll
         for (int i = 0; i < MV; ++i) {
-            const int v = threadIdx.x + i * kThreads;
+            const int v = threadIdx.x + i * NT;
             if (v < nvox) {
                 const long long gi = base + v;
                 T e[6];
@@ -811,7 +853,7 @@ __global__ __launch_bounds__(kThreads) void k_xinv(const cx<T>* __restrict__ S1,
         __syncthreads();
         double* red = reinterpret_cast<double*>(tw + nx);
         double v[1] = {inc};
-        wg_sum_store<1>(v, part_inc + blockIdx.x, red);
+        wg_sum_store<1, NT>(v, part_inc + blockIdx.x, red);
     }
 }
 
@@ -1473,27 +1515,6 @@ __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ 
     wg_sum_store<3>(acc, part + (long long)blockIdx.x * 3, red);
 }
 
-// y -= a x ; part[b] = y.y (Frobenius).
-__global__ __launch_bounds__(kThreads) void k_axpy_norm(double* __restrict__ y, const double* __restrict__ x,
-                                                        double a, long long N, double* __restrict__ part)
-{
-    __shared__ double red[kWaves + 1];
-    double acc[1] = {0.0};
-    const long long b0 = (long long)blockIdx.x * kChunk;
-    for (int i = 0; i < kChunk / kThreads; ++i) {
-        const long long v = b0 + threadIdx.x + i * kThreads;
-        if (v >= N) break;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            const long long o = c * N + v;
-            const double t = y[o] - a * x[o];
-            y[o] = t;
-            acc[0] += frob_w(c) * t * t;
-        }
-    }
-    wg_sum_store<1>(acc, part + blockIdx.x, red);
-}
-
 // RPM recombination eps = xi + sum_j d_j Z_j as a streaming pass: each thread
 // handles runs of VL consecutive elements; for a column, a wave reads one
 // contiguous kilobyte of its tile.  Columns go in groups of 8 whose loads are
@@ -1579,6 +1600,16 @@ __global__ void k_col_put2(const double* __restrict__ v0, const double* __restri
         Z[zix(i, j, zP)] = t;
         out1[i] = t;
     }
+}
+
+// out = (in - a x) * scale in the output type (the second growth candidate:
+// its difference made orthogonal to the first, normalised, to working precision).
+template <typename TO>
+__global__ void k_convert_sub(const double* __restrict__ in, const double* __restrict__ x, double a, double scale,
+                              TO* __restrict__ out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (TO)((in[i] - a * x[i]) * scale);
 }
 
 template <typename TI, typename TO>

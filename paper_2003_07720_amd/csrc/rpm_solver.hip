@@ -47,6 +47,12 @@ constexpr int kTdotsBlocks = RPM_TDOTS_BLOCKS;  // grid cap of the basis product
 #endif
 constexpr bool kGPipe = RPM_GPIPE != 0;        // software-pipelined gamma pass
 constexpr int kGPipeBlocks = RPM_GPIPE_BLOCKS;  // its persistent grid
+#ifndef RPM_X_NT
+#define RPM_X_NT 256
+#endif
+// threads of an FP32 x-pass block (the tile size does not change with it)
+template <typename T>
+constexpr int x_threads() { return sizeof(T) == 4 ? RPM_X_NT : kThreads; }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -144,6 +150,9 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     s.lds_g = (size_t)(2 * ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8;
     if (s.lds_x > (size_t)kLdsCap || s.lds_y > (size_t)kLdsCap || s.lds_g > (size_t)kLdsCap) s.ok = false;
     if (g.ty * g.nx > MV * kThreads) s.ok = false;
+    if ((long long)g.nh * g.ty > (long long)((MV * kThreads / 2 + kMaxTy + kThreads - 1) / kThreads) * kThreads ||
+        g.ty > kMaxTy)
+        s.ok = false;  // spectrum slots of the x-inverse prefetch
     g.fnx = make_fdiv(g.nx);
     for (int a = 0; a < 3; ++a) g.kh[a] = 2.0 * 3.14159265358979323846 / (double)n[a];
     g.fny = make_fdiv(g.ny);
@@ -398,9 +407,10 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     const bool pol = c.pol && out_mode == OUT_XI;
     c.mark_begin(RPM_K_XFWD, ev);
     const bool vec = g.nx % (16 / (int)sizeof(T)) == 0;
+    constexpr int XT = x_threads<T>();
 #define RPM_XFWD(V, P)                                                                                         \
-    k_xfwd<T, V, P><<<sh.G1, kThreads, sh.lds_x, c.s>>>(xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, \
-                                                        g, sh.px, c.twx(), done)
+    k_xfwd<T, V, P, XT><<<sh.G1, XT, sh.lds_x, c.s>>>(xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, \
+                                                      g, sh.px, c.twx(), done)
     if (pol) {
         if (vec) RPM_XFWD(true, true);
         else RPM_XFWD(false, true);
@@ -444,12 +454,12 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     }
     c.mark_begin(RPM_K_XINV, ev);
     if (pol)
-        k_xinv<T, true><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,
-                                                            c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta, done);
+        k_xinv<T, true, XT><<<sh.G1, XT, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,
+                                                          c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta, done);
     else
-        k_xinv<T, false><<<sh.G1, kThreads, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g,
-                                                             sh.px, c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta,
-                                                             done);
+        k_xinv<T, false, XT><<<sh.G1, XT, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g,
+                                                           sh.px, c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta,
+                                                           done);
     c.mark_end(RPM_K_XINV, ev, bi + (pol ? (double)g.N : 0.0));
     c.check_launch();
 }
@@ -694,7 +704,6 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
                int* jvps)
 {
     const long long N = c.sh.g.N;
-    const int Gg = c.sh.Gg;
     double* D1 = c.template at<double>(c.L.D1);
     double* D0 = c.template at<double>(c.L.D0);
     T* tmp = c.template at<T>(c.L.tmp);
@@ -714,14 +723,12 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     const double T11 = std::sqrt(std::max(gram[0], 0.0));
     double T22 = 0.0;
     int want = 0;
+    // modified Gram-Schmidt QR of [D1, D0]: |D0 - (g01 / g00) D1| from the Gram
+    // entries (the subtraction itself is fused into the second candidate's
+    // conversion below)
+    const double r01 = T11 > 0.0 ? gram[1] / gram[0] : 0.0;
     if (T11 > 0.0) {
-        if (two) {
-            k_axpy_norm<<<Gg, kThreads, 0, c.s>>>(D0, D1, gram[1] / gram[0], N, c.pg());
-            reduce_cols(c, c.pg(), Gg, 1, 1, 1, c.gsum());
-            double n2;
-            if (!sync_read(c, &n2, c.gsum(), sizeof(n2))) return -1;
-            T22 = std::sqrt(std::max(n2, 0.0));
-        }
+        if (two) T22 = std::sqrt(std::max(gram[2] - r01 * gram[1], 0.0));
         want = (two && T22 > o->kappa * T11) ? 2 : 1;
     }
     if (o->replay && growth_index < o->replay_len) want = o->replay[growth_index];
@@ -730,13 +737,13 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     // compatible fields (Lippmann-Schwinger map) and back in FP64
     const long long nel = 6 * N;
     const int gb = (int)((nel + 255) / 256);
-    double* cand[2];
-    int nc = 0;
-    for (int col = 0; col < want && col < 2; ++col) {
+    // (the second first: its conversion reads the first difference)
+    const bool use[2] = {want >= 1 && T11 > 0.0, want >= 2 && two && T22 > 0.0};
+    for (int col = 1; col >= 0; --col) {
+        if (!use[col]) continue;
         double* v = col == 0 ? D1 : D0;
-        const double nrm = col == 0 ? T11 : T22;
-        if (!(nrm > 0.0) || (col == 1 && !two)) continue;
-        k_convert<double, T><<<gb, 256, 0, c.s>>>(v, tmp, 1.0 / nrm, nel);
+        if (col == 0) k_convert<double, T><<<gb, 256, 0, c.s>>>(D1, tmp, 1.0 / T11, nel);
+        else k_convert_sub<T><<<gb, 256, 0, c.s>>>(D0, D1, r01, 1.0 / T22, tmp, nel);
         if (c.pol) {
             // polarization iterates are not compatible: the differences stay as they are
             k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp, v, 1.0, nel);
@@ -744,8 +751,11 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
             project_compatible<T>(c, tmp, tmp2);
             k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, v, 1.0, nel);
         }
-        cand[nc++] = v;
     }
+    double* cand[2];
+    int nc = 0;
+    for (int col = 0; col < 2; ++col)
+        if (use[col]) cand[nc++] = col == 0 ? D1 : D0;
     int added = 0;
     if (nc == 2 && p + 2 <= c.pmax && p <= 32) {
         const int r = add_columns<T, 2>(c, p, cand, jvps);
