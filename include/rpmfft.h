@@ -128,6 +128,10 @@ typedef struct {
                                  point operation of both schemes (Sec. 5.5: RPM
                                  around the polarization iteration)              */
     double alpha, beta;       /* polarization parameters (> 0; default 2, 2)     */
+    int32_t profile_classes;  /* with profile = 1: the kernel classes timed, bit
+                                 k for class k (< 1 << RPM_NKERNEL); 0 = every
+                                 class.  Fewer classes, fewer event records
+                                 between the kernels of the timed solve.         */
 } rpm_options;
 
 typedef struct {
@@ -154,7 +158,8 @@ typedef struct {
 
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
  * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
- * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2. */
+ * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2,
+ * no profiling (profile_classes 0). */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and

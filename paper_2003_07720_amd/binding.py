@@ -42,7 +42,8 @@ class RpmOptions(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("reuse_basis", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("replay", ctypes.POINTER(ctypes.c_int32)), ("replay_len", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double),
-                ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double)]
+                ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("profile_classes", ctypes.c_int32)]
 
 
 class RpmStats(ctypes.Structure):

@@ -299,9 +299,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
         const int kx = b % g.nh;
         const int c = b / g.nh;
         const int z0 = zt * tz;
+        // per-element offsets are recomputed per tile, not kept in registers
+        // across the loop (the inverse pass would spill them)
+        int opq = 0;
+        asm volatile("" : "+s"(opq));
 #pragma unroll
         for (int u = 0; u < PT; ++u) {
-            const int e = threadIdx.x + u * kThreads;
+            const int e = threadIdx.x + opq + u * kThreads;
             if (e < nel) {
                 if (D < 0) {
                     pre[u] = Sin[(long long)c * g.nspec + ((long long)kx * g.nz + z0) * ny + e];
@@ -729,9 +733,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     auto load_spec = [&](int q) {
         const cx<T>* ina = S1 + (long long)(2 * q) * g.nspec;
         const cx<T>* inb = S1 + (long long)(2 * q + 1) * g.nspec;
+        int opq = 0;  // offsets recomputed per pair rather than held in registers
+        asm volatile("" : "+s"(opq));
 #pragma unroll
         for (int u = 0; u < KS; ++u) {
-            const int t = threadIdx.x + u * NT;
+            const int t = threadIdx.x + opq + u * NT;
             if (t < nspt) {
                 const int k = g.fty.div(t);
                 const int r = t - k * ty;

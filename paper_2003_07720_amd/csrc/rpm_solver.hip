@@ -267,6 +267,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
 // ---------------------------------------------------------------------------
 struct Prof {
     bool on = false;
+    uint32_t mask = ~0u;  // kernel classes recorded
     std::vector<hipEvent_t> pool;
     struct Rec {
         hipEvent_t a, b;
@@ -355,7 +356,7 @@ struct Ctx {
     void mark_begin(int k, hipEvent_t& a)
     {
         a = nullptr;
-        if (!prof.on) return;
+        if (!prof.on || !((prof.mask >> k) & 1u)) return;
         a = prof.get();
         if (a) hipEventRecord(a, s);
     }
@@ -1049,6 +1050,7 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->refine < 0 || !finite(o->refine_tol) || !(o->refine_tol > 0.0) || !(o->refine_tol < 1.0))
         return RPM_E_INVALID;
     if (o->map != RPM_MAP_LS && o->map != RPM_MAP_POLARIZATION) return RPM_E_INVALID;
+    if (o->profile_classes < 0 || o->profile_classes >= (1 << RPM_NKERNEL)) return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
         return RPM_E_INVALID;
@@ -1077,6 +1079,7 @@ rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void
     c.alpha = o->alpha;
     c.beta = o->beta;
     c.prof.on = o->profile != 0;
+    c.prof.mask = o->profile_classes ? (uint32_t)o->profile_classes : ~0u;
     return RPM_OK;
 }
 
@@ -1171,6 +1174,7 @@ void rpm_default_options(rpm_options* o)
     o->refine = 4;
     o->refine_tol = 1e-3;
     o->map = RPM_MAP_LS;
+    o->profile_classes = 0;
     o->alpha = 2.0;
     o->beta = 2.0;
 }
