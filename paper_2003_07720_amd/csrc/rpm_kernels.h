@@ -24,6 +24,21 @@
 
 namespace rpm {
 
+// 16-byte non-temporal loads: the per-step basis streams read 50 MB per column
+// and would otherwise push the fields the FFT passes re-read out of the caches
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 nt_load(const float4* p)
+{
+    const nt_f4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+    return make_float4(t.x, t.y, t.z, t.w);
+}
+__device__ __forceinline__ double2 nt_load(const double2* p)
+{
+    const nt_d2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_d2*>(p));
+    return make_double2(t.x, t.y);
+}
+
 struct Geo {
     int nx, ny, nz, nh;    // nh = nx/2 + 1 (half spectrum along x)
     long long N;           // voxels
@@ -874,6 +889,13 @@ template <>
 struct Raw4<float> {
     float4 v;
     __device__ __forceinline__ void load(const float* __restrict__ p) { v = *reinterpret_cast<const float4*>(p); }
+    // NT: non-temporal (a basis stream that would only evict the fields from the caches)
+    template <bool NT>
+    __device__ __forceinline__ void load_s(const float* __restrict__ p)
+    {
+        if constexpr (NT) v = nt_load(reinterpret_cast<const float4*>(p));
+        else v = *reinterpret_cast<const float4*>(p);
+    }
     __device__ __forceinline__ void load_tail(const float* __restrict__ p, long long e0, long long L6)
     {
         v.x = e0 < L6 ? p[0] : 0.f;
@@ -896,6 +918,16 @@ struct Raw4<double> {
     {
         a = *reinterpret_cast<const double2*>(p);
         b = *reinterpret_cast<const double2*>(p + 2);
+    }
+    template <bool NT>
+    __device__ __forceinline__ void load_s(const double* __restrict__ p)
+    {
+        if constexpr (NT) {
+            a = nt_load(reinterpret_cast<const double2*>(p));
+            b = nt_load(reinterpret_cast<const double2*>(p + 2));
+        } else {
+            load(p);
+        }
     }
     __device__ __forceinline__ void load_tail(const double* __restrict__ p, long long e0, long long L6)
     {
@@ -926,7 +958,7 @@ struct Fields {
 // same field slice (one HBM read, the rest from cache).  Slices are addressed
 // as a wave-uniform base plus the lane offset.  Partial sums are
 // column-major: part[(f * ld + j) * G + b], G = gridDim.x.
-template <bool FULL, typename TA, typename TZ, int NF>
+template <bool FULL, typename TA, typename TZ, int NF, bool NT>
 __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, const TZ* __restrict__ zt, int lo,
                                            int nj, long long e0, long long L6, long long N3,
                                            double (&acc)[NF][8])
@@ -946,7 +978,7 @@ __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, co
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         const TZ* zc = zt + (long long)min(u, nj - 1) * kZTile;
-        if (FULL) raw[u].load(zc + lo);
+        if (FULL) raw[u].template load_s<NT>(zc + lo);
         else raw[u].load_tail(zc + lo, e0, L6);
     }
 #pragma unroll
@@ -966,8 +998,8 @@ __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, co
     }
 }
 
-// SITE only separates the call sites in profiles (0: the per-step
-// projections, 1: basis growth); the code is the same.
+// SITE separates the call sites (0: the per-step projections, 1: basis
+// growth); the per-step stream reads the basis with non-temporal loads.
 template <typename TA, typename TZ, int NF, int SITE>
 __global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restrict__ Z, int p, int zP, long long N,
                                                double* __restrict__ part, int ld)
@@ -986,10 +1018,10 @@ __global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restric
         for (int u = 0; u < 8; ++u) acc[f][u] = 0.0;
     long long tile = blockIdx.x;
     for (; tile < nfull; tile += gridDim.x)
-        gdots_tile<true, TA, TZ, NF>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+        gdots_tile<true, TA, TZ, NF, SITE == 0>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
                                      tile * kZTile + lo, L6, N3, acc);
     if (tile == nfull && nfull * kZTile < L6)  // the last, partial tile
-        gdots_tile<false, TA, TZ, NF>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+        gdots_tile<false, TA, TZ, NF, SITE == 0>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
                                       tile * kZTile + lo, L6, N3, acc);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -1043,7 +1075,7 @@ __device__ __forceinline__ void tdots_tile(TA* __restrict__ a0, TA* __restrict__
 #pragma unroll
         for (int u = 0; u < CG; ++u) {
             const TZ* zc = zt + (long long)min(g * CG + u, p - 1) * kZTile;
-            if (FULL) raw[u].load(zc);
+            if (FULL) raw[u].template load_s<false>(zc);
             else raw[u].load_tail(zc, e0, L6);
         }
     };
@@ -1524,7 +1556,8 @@ __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ 
 // RPM recombination eps = xi + sum_j d_j Z_j as a streaming pass: each thread
 // handles runs of VL consecutive elements; for a column, a wave reads one
 // contiguous kilobyte of its tile.  Columns go in groups of 8 whose loads are
-// issued together; slots past p repeat column p - 1 with coefficient zero.
+// issued together (non-temporal); slots past p repeat column p - 1 with
+// coefficient zero.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi, const T* __restrict__ Z, int p,
                                                         int zP, const double* __restrict__ dco,
@@ -1546,7 +1579,8 @@ __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi
         for (int g = 0; g < p; g += 8) {
             V z[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) z[u] = *reinterpret_cast<const V*>(zt + (long long)min(g + u, p - 1) * kZTile);
+            for (int u = 0; u < 8; ++u)
+                z[u] = nt_load(reinterpret_cast<const V*>(zt + (long long)min(g + u, p - 1) * kZTile));
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const T* zs = reinterpret_cast<const T*>(&z[u]);
