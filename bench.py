@@ -119,7 +119,7 @@ def parse():
                     help="looser tolerances timed for RPM and the basic scheme (comma list, '' = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle map applications in the CPU sample")
+    ap.add_argument("--cpu-steps", type=int, default=14, help="oracle map applications in the CPU sample")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a float32 buffer of this many MiB three times (a plain copy kernel "
                          "of known size that scales hardware byte counters)")
