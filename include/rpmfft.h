@@ -214,6 +214,26 @@ rpm_status rpm_fft_solve(const rpm_problem *pr, const double E[6], const rpm_opt
 rpm_status rpm_fft_effective_tensor(const rpm_problem *pr, const rpm_options *o, double *C_eff, rpm_stats *st,
                                     void *workspace, size_t ws_bytes, void *hip_stream);
 
+/*
+ * Seed the unstable-subspace basis of a workspace (a warm start of Z for the
+ * next rpm_fft_solve / rpm_fft_effective_tensor with reuse_basis set; Sec. 3:
+ * any orthonormal Z with H = Z^T F_u Z serves the Newton step).  Each vector
+ * goes through the steps basis growth (Algorithm 2, In(q, Z)) applies to a
+ * difference of iterates: normalised, projected onto zero-mean compatible
+ * fields (Lippmann-Schwinger map), re-orthogonalised twice against the basis
+ * and dropped if its norm falls to 1e-10 or below, then one Jacobian-vector
+ * product for its column of W and its border of H.  Columns are appended to
+ * the basis the workspace holds when o->reuse_basis is set (else to an empty
+ * one), up to o->p_max; o->scheme must be RPM_SCHEME_RPM.
+ *   V      DEVICE [p0][6][N] fields in o->precision (read only; may be NULL
+ *          when p0 == 0).
+ *   p_out  HOST nullable: the basis dimension afterwards.
+ * Errors: RPM_E_INVALID for p0 < 0, a NULL V with p0 > 0 or the basic scheme,
+ * before any device work.
+ */
+rpm_status rpm_fft_seed_basis(const rpm_problem *pr, const rpm_options *o, const void *V, int32_t p0, int32_t *p_out,
+                              void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Current basis dimension stored in a workspace (0 if never used).  HOST p. */
 rpm_status rpm_workspace_basis_dim(const void *workspace, size_t ws_bytes, int32_t *p, void *hip_stream);
 

@@ -73,6 +73,8 @@ def _load():
         lib.orc_solve.argtypes = [i, i, i, u8p, dp, d, d, dp, i, d, i, i, i, d, ip, i, dp, dp, dp, dp, ip,
                                   dp, dp, ip, dp, dp, i, ip, i, i, d, d]
         lib.orc_solve.restype = i
+        lib.orc_seed_basis.argtypes = [i, i, i, u8p, dp, d, d, dp, i, i, dp, dp, dp, ip, i, d, d]
+        lib.orc_seed_basis.restype = i
         _lib = lib
     return _lib
 
@@ -243,6 +245,23 @@ def solve(phase, lame_tab, lame0, E, scheme="rpm", tol=1e-8, max_iter=10000, n_m
     return dict(eps=eps, sig_avg=sav, status=STATUS[st], iterations=it, jvps=int(counters[1]),
                 growth=int(counters[2]), p=int(counters[3]), residual=float(res[0]), max_imag=float(res[1]),
                 history=hist[:min(it, hist_cap)].copy(), decisions=dec[:int(counters[2])].copy(), basis=basis)
+
+
+def seed_basis(phase, lame_tab, lame0, V, basis, map="classical", alpha=2.0, beta=2.0):
+    """Append the vectors V (k, 6, nz, ny, nx) to the basis the way growth adds a
+    difference of iterates (normalise, compatible projection for the classical
+    map, two Gram-Schmidt passes, drop below 1e-10), with their W = F_u z columns
+    and H borders.  Returns the number of columns added; basis.p is updated."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    nz, ny, nx = phase.shape
+    lt = np.ascontiguousarray(lame_tab, dtype=np.float64)
+    V = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1, 6 * nx * ny * nz))
+    p_io = np.array([basis.p], dtype=np.int32)
+    added = _load().orc_seed_basis(nx, ny, nz, _u8(phase), _dp(lt), float(lame0[0]), float(lame0[1]), _dp(V),
+                                   V.shape[0], basis.p_max, _dp(basis.Z), _dp(basis.W), _dp(basis.H), _ip(p_io),
+                                   MAPS[map], float(alpha), float(beta))
+    basis.p = int(p_io[0])
+    return int(added)
 
 
 def unit_load(j):

@@ -835,3 +835,46 @@ int orc_solve(int nx, int ny, int nz, const unsigned char *phase, const double *
     free(eps);
     return status;
 }
+
+/*
+ * Seed the unstable-subspace basis with given vectors (a warm start of Z; any
+ * orthonormal Z with H = Z^T F_u Z serves the Newton step of Sec. 3).  Each of
+ * the p0 vectors V[k] (6N doubles, read only) goes through the steps basis
+ * growth applies to a difference of iterates: normalised, projected onto
+ * zero-mean compatible fields (map 0), added after two classical Gram-Schmidt
+ * passes (dropped below 1e-10 of its norm), then its JVP column of W
+ * (F(z; E = 0)) and its border of H.  Z, W, H and *p_io as in orc_solve: the
+ * *p_io columns already held are kept and new ones appended up to p_max.
+ * Returns the number of columns added.
+ */
+int orc_seed_basis(int nx, int ny, int nz, const unsigned char *phase, const double *lame, double lam0, double mu0,
+                   const double *V, int p0, int p_max, double *Z, double *W, double *H, int *p_io, int map,
+                   double alpha, double beta)
+{
+    problem pr;
+    init_problem(&pr, nx, ny, nz, phase, lame, lam0, mu0);
+    pr.map = map;
+    pr.alpha = alpha;
+    pr.beta = beta;
+    long N = pr.N, L = 6 * N;
+    int p = *p_io, added = 0;
+    double *v = (double *)malloc(sizeof(double) * L);
+    double zero6[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < p0 && p < p_max; ++k) {
+        memcpy(v, V + k * L, sizeof(double) * L);
+        double nv = sqrt(fdot(N, v, v));
+        if (!(nv > 0.0)) continue;
+        for (long i = 0; i < L; ++i) v[i] /= nv;
+        if (map == 0) project_compatible(&pr, v);
+        if (!add_column(N, Z, p, v, 1.0)) continue;
+        double e_dummy, s_dummy[6];
+        fmap(&pr, zero6, Z + p * L, W + p * L, &e_dummy, s_dummy);
+        for (int i = 0; i <= p; ++i) H[i * p_max + p] = fdot(N, Z + i * L, W + p * L);
+        for (int j = 0; j < p; ++j) H[p * p_max + j] = fdot(N, Z + p * L, W + j * L);
+        ++p;
+        ++added;
+    }
+    *p_io = p;
+    free(v);
+    return added;
+}

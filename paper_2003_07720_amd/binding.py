@@ -69,14 +69,16 @@ _lib.rpm_fft_solve.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _v
 _lib.rpm_fft_effective_tensor.argtypes = [_P(RpmProblem), _P(RpmOptions), _dp, _P(RpmStats), _vp, ctypes.c_size_t,
                                           _vp]
 _lib.rpm_workspace_basis_dim.argtypes = [_vp, ctypes.c_size_t, _P(ctypes.c_int32), _vp]
+_lib.rpm_fft_seed_basis.argtypes = [_P(RpmProblem), _P(RpmOptions), _vp, ctypes.c_int32, _P(ctypes.c_int32), _vp,
+                                    ctypes.c_size_t, _vp]
 _lib.rpm_status_string.argtypes = [ctypes.c_int]
 _lib.rpm_status_string.restype = ctypes.c_char_p
 for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve", "rpm_fft_effective_tensor",
-           "rpm_workspace_basis_dim"):
+           "rpm_workspace_basis_dim", "rpm_fft_seed_basis"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve",
-            "rpm_fft_effective_tensor", "rpm_workspace_basis_dim", "rpm_status_string"]
+            "rpm_fft_effective_tensor", "rpm_fft_seed_basis", "rpm_workspace_basis_dim", "rpm_status_string"]
 
 
 class RpmError(RuntimeError):
@@ -257,6 +259,24 @@ def effective_tensor(phase, lame_tab, lame0, opts=None, workspace=None, history_
         raise RpmError(rc, "rpm_fft_effective_tensor")
     stats = [_stats_dict(sts[i], keep[i][0], keep[i][1]) for i in range(nc)]
     return np.array(C[:]).reshape(nc, nc), stats, status_string(rc)
+
+
+def seed_basis(phase, lame_tab, lame0, V, opts, workspace):
+    """Append the fields V (k, 6, nz, ny, nx; device, field dtype) to the workspace's
+    basis (rpm_fft_seed_basis; opts.reuse_basis keeps the basis already held).
+    Returns the basis dimension afterwards."""
+    shape = tuple(phase.shape)
+    dt = field_dtype(opts)
+    if not (isinstance(V, torch.Tensor) and V.is_cuda and V.dtype == dt and V.is_contiguous()
+            and tuple(V.shape[1:]) == (6,) + shape):
+        raise ValueError(f"V must be a contiguous {dt} device tensor of shape (k, 6) + {shape}")
+    pr = _problem(phase, lame_tab, lame0)
+    p = ctypes.c_int32()
+    rc = _lib.rpm_fft_seed_basis(ctypes.byref(pr), ctypes.byref(opts), V.data_ptr() if V.shape[0] else None,
+                                 V.shape[0], ctypes.byref(p), workspace.data_ptr(), workspace.numel(), _stream())
+    if rc < 0:
+        raise RpmError(rc, "rpm_fft_seed_basis")
+    return p.value
 
 
 def basis_dim(workspace):

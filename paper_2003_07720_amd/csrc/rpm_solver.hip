@@ -1122,6 +1122,59 @@ rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_optio
     return RPM_OK;
 }
 
+// Basis seed (warm start of Z): each vector goes through the steps growth
+// applies to a difference of iterates (normalise, compatible projection for
+// the Lippmann-Schwinger map, two Gram-Schmidt passes, JVP, H and Gram
+// borders), appended to the basis the workspace holds when o->reuse_basis is
+// set, else to an empty one.
+template <typename T>
+rpm_status seed_typed(const rpm_problem* pr, const rpm_options* o, const void* V, int p0, int32_t* p_out, void* ws,
+                      size_t ws_bytes, void* stream)
+{
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    if (c.pmax == 0) return RPM_E_INVALID;
+    int p = 0;
+    rs = prepare(c, pr, o, o->reuse_basis != 0, &p, o->tol);
+    if (rs != RPM_OK) return rs;
+    const long long N = c.sh.g.N;
+    const long long nel = 6 * N;
+    const int gb = (int)((nel + 255) / 256);
+    const int rs_ = 2 * kMaxP + 3;
+    double* D1 = c.template at<double>(c.L.D1);
+    T* tmp = c.template at<T>(c.L.tmp);
+    T* tmp2 = c.template at<T>(c.L.tmp2);
+    double* nr = c.gx() + 4 * kMaxP;
+    int added = 0, jvps = 0;
+    for (int k = 0; k < p0 && p < c.pmax; ++k) {
+        const T* v = reinterpret_cast<const T*>(V) + (long long)k * nel;
+        k_convert<T, double><<<gb, 256, 0, c.s>>>(v, D1, 1.0, nel);
+        // its norm: an update pass against no columns
+        launch_update<T, 1, true>(c.s, c.sh.Gq, D1, nullptr, c.Zb(), 0, c.pmax, nullptr, N, c.pg(), rs_);
+        reduce_cols(c, c.pg() + kMaxP, c.sh.Gq, rs_, 1, 1, nr);
+        double n2 = 0.0;
+        if (!sync_read(c, &n2, nr, sizeof(n2))) return RPM_E_HIP;
+        if (!(n2 > 0.0) || !finite(n2)) continue;
+        k_convert<double, T><<<gb, 256, 0, c.s>>>(D1, tmp, 1.0 / std::sqrt(n2), nel);
+        if (c.pol) {
+            k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp, D1, 1.0, nel);
+        } else {
+            project_compatible<T>(c, tmp, tmp2);
+            k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp2, D1, 1.0, nel);
+        }
+        double* cand[1] = {D1};
+        const int r = add_columns<T, 1>(c, p, cand, &jvps);
+        if (r < 0) return RPM_E_HIP;
+        added += r;
+    }
+    if (added > 0) k_factor<<<1, 64, 0, c.s>>>(c.st, p);
+    c.check_launch();
+    if (hipStreamSynchronize(c.s) != hipSuccess || c.hip_error) return RPM_E_HIP;
+    if (p_out) *p_out = p;
+    return RPM_OK;
+}
+
 template <typename T>
 rpm_status eff_typed(const rpm_problem* pr, const rpm_options* o, double* C, rpm_stats* st, void* ws,
                      size_t ws_bytes, void* stream)
@@ -1241,6 +1294,16 @@ rpm_status rpm_fft_effective_tensor(const rpm_problem* pr, const rpm_options* o,
     if (!C_eff) return RPM_E_INVALID;
     if (o->precision == RPM_FP64) return eff_typed<double>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
     return eff_typed<float>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
+}
+
+rpm_status rpm_fft_seed_basis(const rpm_problem* pr, const rpm_options* o, const void* V, int32_t p0, int32_t* p_out,
+                              void* workspace, size_t ws_bytes, void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (p0 < 0 || (p0 > 0 && !V) || o->scheme != RPM_SCHEME_RPM) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64) return seed_typed<double>(pr, o, V, p0, p_out, workspace, ws_bytes, hip_stream);
+    return seed_typed<float>(pr, o, V, p0, p_out, workspace, ws_bytes, hip_stream);
 }
 
 rpm_status rpm_workspace_basis_dim(const void* workspace, size_t ws_bytes, int32_t* p, void* hip_stream)

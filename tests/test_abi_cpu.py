@@ -145,6 +145,24 @@ def test_solve_rejects_bad_arguments_before_device_work(B, case):
         assert rc == expect, (case, rc)
 
 
+def test_seed_basis_rejects_bad_arguments(B):
+    lib = B._lib
+    pr = _raw_problem(B)
+    p = ctypes.c_int32(-7)
+    o = B.make_options()
+    assert lib.rpm_fft_seed_basis(ctypes.byref(pr), ctypes.byref(o), 0x3000, -1, ctypes.byref(p), 0x2000, 1 << 40,
+                                  None) == -1
+    assert lib.rpm_fft_seed_basis(ctypes.byref(pr), ctypes.byref(o), None, 2, ctypes.byref(p), 0x2000, 1 << 40,
+                                  None) == -1
+    ob = B.make_options(scheme="basic")
+    assert lib.rpm_fft_seed_basis(ctypes.byref(pr), ctypes.byref(ob), 0x3000, 1, ctypes.byref(p), 0x2000, 1 << 40,
+                                  None) == -1
+    o.tol = 0.0
+    assert lib.rpm_fft_seed_basis(ctypes.byref(pr), ctypes.byref(o), 0x3000, 1, ctypes.byref(p), 0x2000, 1 << 40,
+                                  None) == -1
+    assert p.value == -7  # untouched
+
+
 def test_apply_rejects_aliasing_and_nulls(B):
     lib = B._lib
     o = B.make_options()

@@ -370,6 +370,61 @@ def test_rpm_complete_basis_one_newton_step():
     np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
 
 
+def test_seed_basis_columns_and_drop_rule():
+    """Seeded columns are orthonormal, lie in the compatible space of an explicit
+    basis, span the seeds' compatible parts; H = Z^T W; a seed already in the span
+    is dropped."""
+    shape = (2, 4, 6)
+    ph = M.random_phases(shape, 2, seed=71)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(20, 0.3)])
+    l0 = CF.lame(10.5, 0.3)
+    seeds = np.stack([M.random_field(shape, seed=72 + k) for k in range(3)])
+    b = O.Basis(shape, 8)
+    assert O.seed_basis(ph, lt, l0, seeds, b) == 3 and b.p == 3
+    Z = b.Z[:3].reshape(3, 6, -1)
+    w = np.array([1, 1, 1, 2, 2, 2])[None, :, None]
+    np.testing.assert_allclose(np.einsum("acx,bcx->ab", Z * w, Z), np.eye(3), atol=1e-12)
+    V = CF.compatible_basis(shape)  # orthonormal, Mandel components
+    Zm = (Z * CF.MANDEL_W[None, :, None]).reshape(3, -1)
+    np.testing.assert_allclose(V @ (V.T @ Zm.T), Zm.T, atol=1e-12)
+    # the compatible part of every seed, in the sense of the projection Gamma0 C0
+    # (orthogonal in the C0 energy: c = V (V^T C0 V)^-1 V^T C0 g), is in span(Z)
+    C0 = CF.iso_mandel(*l0)
+
+    def c0(x):
+        return (C0 @ x.reshape(6, -1)).ravel()
+
+    C0V = np.stack([c0(V[:, j]) for j in range(V.shape[1])], axis=1)
+    for k in range(3):
+        gm = (seeds[k].reshape(6, -1) * CF.MANDEL_W[:, None]).ravel()
+        pc = V @ np.linalg.solve(V.T @ C0V, V.T @ c0(gm))
+        res = pc - Zm.T @ (Zm @ pc)
+        assert np.abs(res).max() <= 1e-11 * np.abs(pc).max()
+    W = b.W[:3].reshape(3, 6, -1)
+    np.testing.assert_allclose(b.H[:3, :3], np.einsum("acx,bcx->ab", Z * w, W), atol=1e-12)
+    # the seeds again: nothing new
+    assert O.seed_basis(ph, lt, l0, seeds, b) == 0 and b.p == 3
+
+
+def test_seed_basis_complete_space_one_newton_step():
+    """Seeded with a basis of the whole compatible space, RPM lands on the direct
+    (Galerkin) solution after one Newton step, so W and H are right."""
+    shape = (1, 4, 4)
+    ph = M.random_phases(shape, 2, seed=41)
+    lt = np.array([CF.lame(1, 0.3), CF.lame(1000, 0.3)])
+    l0 = CF.lame(2.0, 0.3)  # the plain fixed point diverges here
+    E = np.array([0.01, 0.003, 0, 0, 0, -0.002])
+    V = CF.compatible_basis(shape)
+    seeds = (V.reshape(6, -1, V.shape[1]) / CF.MANDEL_W[:, None, None]).transpose(2, 0, 1)
+    p = V.shape[1]
+    b = O.Basis(shape, p)
+    assert O.seed_basis(ph, lt, l0, seeds.reshape((p, 6) + shape), b) == p
+    r = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-11, max_iter=10, p_max=p, basis=b)
+    assert r["status"] == "converged" and r["iterations"] == 2
+    ref_eps, _ = CF.galerkin_solution(ph, lt, E)
+    np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
+
+
 def test_basic_diverges_below_half_max_modulus():
     """Classical scheme: spectrum of F_u in [1 - E_max/E0, 1 - E_min/E0] (equal nu); a
     reference modulus below E_max / 2 puts an eigenvalue below -1 and the iteration
