@@ -126,6 +126,9 @@ def parse():
     ap.add_argument("--table1", action="store_true",
                     help="instead of the benchmark: the contrast sweep of Sec. 5.5 (128^2 fibre, polarization "
                          "iteration alone and with RPM, FP64, tol 1e-4); prints its own JSON line")
+    ap.add_argument("--stress", action="store_true",
+                    help="instead of the benchmark: a prescribed-mean-stress solve of the 64^3 sphere workload "
+                         "(FP64 and FP32 refined), timed; prints its own JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --warmup 0 --no-cpu --no-ttt --calibrate-copy-mib M' into per-launch traffic "
@@ -176,6 +179,45 @@ def table1():
                       "rows": rows}), flush=True)
 
 
+def stress_bench():
+    """Prescribed mean stress on the 64^3 sphere workload: uniaxial Sigma_zz with the
+    other components zero, RPM, tol 1e-6 (FP64, and FP32 fields refined to an
+    FP64-certified 1e-6), timed after one untimed solve of the same call."""
+    import torch
+
+    from paper_2003_07720_amd import binding as B
+    from paper_2003_07720_amd import microstructure as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = M.workload_spheres64(ref_index=2)  # E0 at the arithmetic mean of the phase moduli
+    phase = torch.from_numpy(w["phase"]).to("cuda")
+    lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
+    l0 = B.lame_from_young(*w["ref"])
+    S = np.array([0.0, 0.0, 0.01, 0.0, 0.0, 0.0])
+    rows = {}
+    for prec in ("fp64", "fp32"):
+        opts = B.make_options(scheme="rpm", precision=prec, tol=1e-6, n_max=10, p_max=32, check_every=32,
+                              max_iter=20000)
+        ws = B.make_workspace(tuple(phase.shape), opts)
+        B.fft_solve_stress(phase, lt, l0, S, opts, workspace=ws, want_eps=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = B.fft_solve_stress(phase, lt, l0, S, opts, workspace=ws, want_eps=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        its = sum(c["iterations"] for c in r["cases"]) + r["final"]["iterations"]
+        rows[prec] = dict(status=r["status"], seconds=round(el, 4), iterations=its,
+                          final_iterations=r["final"]["iterations"], E=[round(x, 9) for x in r["E"]],
+                          sig_avg=[round(x, 9) for x in r["sig_avg"]],
+                          voxel_iters_per_s=round(phase.numel() * its / el, 1))
+        print(f"stress: {prec} {rows[prec]}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "seconds per prescribed-mean-stress solve, 64^3 spheres", "n_gpus": 1,
+                      "data": "synthetic",
+                      "config": {"workload": "64^3 random spheres (radii 4-8, vf 0.2, seed 2000), E 1 / 1000, "
+                                             "E0 500.5, Sigma_zz = 0.01, RPM p_max 32, tol 1e-6"},
+                      "rows": rows}), flush=True)
+
+
 def main():
     a = parse()
     if a.traffic_from:
@@ -184,6 +226,9 @@ def main():
         return
     if a.table1 and a.gpus == 1:
         table1()
+        return
+    if a.stress and a.gpus == 1:
+        stress_bench()
         return
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} refused: this build runs on a single GPU (one process, one device); "

@@ -234,6 +234,27 @@ rpm_status rpm_fft_effective_tensor(const rpm_problem *pr, const rpm_options *o,
 rpm_status rpm_fft_seed_basis(const rpm_problem *pr, const rpm_options *o, const void *V, int32_t p0, int32_t *p_out,
                               void *workspace, size_t ws_bytes, void *hip_stream);
 
+/*
+ * Solve the cell problem for a prescribed mean stress Sigma (Sec. 2: the
+ * average strain or stress is given).  The problem is linear, so it is the
+ * strain-controlled problem for the mean strain E with C_eff E = Sigma: the
+ * effective stiffness comes from one solve per unit mean strain (as
+ * rpm_fft_effective_tensor, the basis carried from one case to the next),
+ * then E from C_eff (Voigt, engineering shear; 2-D plane strain over 11, 22,
+ * 12, Sigma_33 then being the reaction), then the strain-controlled solve for E.
+ *   Sigma  HOST 6 tensor components (11, 22, 33, 23, 13, 12).
+ *   eps_out, sig_out  DEVICE nullable, as rpm_fft_solve.
+ *   sig_avg, E_out    HOST nullable: <sigma> of eps_out and the mean strain E.
+ *   st     HOST nullable: 7 entries in 3-D (4 in 2-D): the unit load cases,
+ *          then the final solve.
+ * Returns the first non-OK status of the solves, RPM_SINGULAR when C_eff is
+ * singular (pivot below 1e-14 of its largest entry; no final solve), or a
+ * negative code before any device work.
+ */
+rpm_status rpm_fft_solve_stress(const rpm_problem *pr, const double Sigma[6], const rpm_options *o, void *eps_out,
+                                void *sig_out, double sig_avg[6], double E_out[6], rpm_stats *st, void *workspace,
+                                size_t ws_bytes, void *hip_stream);
+
 /* Current basis dimension stored in a workspace (0 if never used).  HOST p. */
 rpm_status rpm_workspace_basis_dim(const void *workspace, size_t ws_bytes, int32_t *p, void *hip_stream);
 

@@ -247,6 +247,25 @@ def solve(phase, lame_tab, lame0, E, scheme="rpm", tol=1e-8, max_iter=10000, n_m
                 history=hist[:min(it, hist_cap)].copy(), decisions=dec[:int(counters[2])].copy(), basis=basis)
 
 
+def solve_stress(phase, lame_tab, lame0, Sigma, **kw):
+    """Prescribed mean stress Sigma (Sec. 2: the average strain or stress is given).
+    The problem is linear: the mean strain E solves C_eff E = Sigma (Voigt with
+    engineering shear; 2-D plane strain over 11, 22, 12), C_eff from one solve per
+    unit mean strain; then the strain-controlled solve for E.  Returns the final
+    solve's dict with E and C_eff added."""
+    phase = np.ascontiguousarray(phase, dtype=np.uint8)
+    two_d = phase.shape[0] == 1
+    idx = [0, 1, 5] if two_d else list(range(6))
+    C, _ = effective_tensor(phase, lame_tab, lame0, **kw)
+    g = np.linalg.solve(C, np.asarray(Sigma, dtype=np.float64)[idx])
+    E = np.zeros(6)
+    for r, i in enumerate(idx):
+        E[i] = g[r] if i < 3 else 0.5 * g[r]
+    out = solve(phase, lame_tab, lame0, E, **kw)
+    out.update(E=E, C_eff=C)
+    return out
+
+
 def seed_basis(phase, lame_tab, lame0, V, basis, map="classical", alpha=2.0, beta=2.0):
     """Append the vectors V (k, 6, nz, ny, nx) to the basis the way growth adds a
     difference of iterates (normalise, compatible projection for the classical

@@ -69,16 +69,19 @@ _lib.rpm_fft_solve.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _v
 _lib.rpm_fft_effective_tensor.argtypes = [_P(RpmProblem), _P(RpmOptions), _dp, _P(RpmStats), _vp, ctypes.c_size_t,
                                           _vp]
 _lib.rpm_workspace_basis_dim.argtypes = [_vp, ctypes.c_size_t, _P(ctypes.c_int32), _vp]
+_lib.rpm_fft_solve_stress.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _dp, _dp, _P(RpmStats), _vp,
+                                      ctypes.c_size_t, _vp]
 _lib.rpm_fft_seed_basis.argtypes = [_P(RpmProblem), _P(RpmOptions), _vp, ctypes.c_int32, _P(ctypes.c_int32), _vp,
                                     ctypes.c_size_t, _vp]
 _lib.rpm_status_string.argtypes = [ctypes.c_int]
 _lib.rpm_status_string.restype = ctypes.c_char_p
 for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve", "rpm_fft_effective_tensor",
-           "rpm_workspace_basis_dim", "rpm_fft_seed_basis"):
+           "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve",
-            "rpm_fft_effective_tensor", "rpm_fft_seed_basis", "rpm_workspace_basis_dim", "rpm_status_string"]
+            "rpm_fft_effective_tensor", "rpm_fft_solve_stress", "rpm_fft_seed_basis", "rpm_workspace_basis_dim",
+            "rpm_status_string"]
 
 
 class RpmError(RuntimeError):
@@ -259,6 +262,43 @@ def effective_tensor(phase, lame_tab, lame0, opts=None, workspace=None, history_
         raise RpmError(rc, "rpm_fft_effective_tensor")
     stats = [_stats_dict(sts[i], keep[i][0], keep[i][1]) for i in range(nc)]
     return np.array(C[:]).reshape(nc, nc), stats, status_string(rc)
+
+
+def fft_solve_stress(phase, lame_tab, lame0, Sigma, opts=None, workspace=None, want_eps=True, want_sig=False,
+                     history_cap=100000):
+    """Solve for a prescribed mean stress Sigma (rpm_fft_solve_stress).  Returns a
+    dict with status, eps, sig (optional), sig_avg, E (the mean strain found) and
+    the statistics of the unit load cases and of the final solve."""
+    opts = opts or make_options()
+    shape = tuple(phase.shape)
+    dt = field_dtype(opts)
+    ws = workspace if workspace is not None else make_workspace(shape, opts)
+    eps = torch.empty((6,) + shape, dtype=dt, device=phase.device) if want_eps else None
+    sig = torch.empty((6,) + shape, dtype=dt, device=phase.device) if want_sig else None
+    pr = _problem(phase, lame_tab, lame0)
+    Sa = (ctypes.c_double * 6)(*[float(x) for x in Sigma])
+    sav = (ctypes.c_double * 6)()
+    Eo = (ctypes.c_double * 6)()
+    ns = 4 if shape[0] == 1 else 7
+    sts = (RpmStats * ns)()
+    keep = []
+    for i in range(ns):
+        hist = np.zeros(history_cap)
+        dec = np.zeros(4096, dtype=np.int32)
+        sts[i].history = hist.ctypes.data_as(_dp)
+        sts[i].history_cap = history_cap
+        sts[i].decisions = dec.ctypes.data_as(_P(ctypes.c_int32))
+        sts[i].decisions_cap = dec.size
+        keep.append((hist, dec))
+    rc = _lib.rpm_fft_solve_stress(ctypes.byref(pr), Sa, ctypes.byref(opts),
+                                   eps.data_ptr() if eps is not None else None,
+                                   sig.data_ptr() if sig is not None else None, sav, Eo, sts, ws.data_ptr(),
+                                   ws.numel(), _stream())
+    if rc < 0:
+        raise RpmError(rc, "rpm_fft_solve_stress")
+    stats = [_stats_dict(sts[i], keep[i][0], keep[i][1]) for i in range(ns)]
+    return dict(status=status_string(rc), code=rc, eps=eps, sig=sig, sig_avg=np.array(sav[:]), E=np.array(Eo[:]),
+                cases=stats[:-1], final=stats[-1], workspace=ws)
 
 
 def seed_basis(phase, lame_tab, lame0, V, opts, workspace):

@@ -1204,6 +1204,74 @@ rpm_status eff_typed(const rpm_problem* pr, const rpm_options* o, double* C, rpm
     return worst;
 }
 
+// Prescribed mean stress (the cell problem "given the average strain or
+// stress" of Sec. 2): the effective stiffness from one solve per unit mean
+// strain (the basis carried from case to case), the mean strain E with
+// C_eff gamma = Sigma (Voigt, engineering shear; 2-D over 11, 22, 12), then
+// the strain-controlled solve for E.  st: nc + 1 entries (the load cases,
+// then the final solve).
+template <typename T>
+rpm_status stress_typed(const rpm_problem* pr, const double S[6], const rpm_options* o, void* eps_out, void* sig_out,
+                        double* sig_avg, double* E_out, rpm_stats* st, void* ws, size_t ws_bytes, void* stream)
+{
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    const bool two_d = pr->n[2] == 1;
+    const int cases3[3] = {0, 1, 5};
+    const int nc = two_d ? 3 : 6;
+    double C[36];
+    rpm_status worst = RPM_OK;
+    for (int col = 0; col < nc; ++col) {
+        const int j = two_d ? cases3[col] : col;
+        double E[6] = {0, 0, 0, 0, 0, 0};
+        E[j] = j < 3 ? 1.0 : 0.5;
+        double sav[6];
+        c.prof.reset();
+        rs = solve_full<T>(c, pr, E, o, nullptr, nullptr, nullptr, sav, st ? st + col : nullptr,
+                           col > 0 || o->reuse_basis != 0);
+        if (rs < 0) return rs;
+        if (rs != RPM_OK && worst == RPM_OK) worst = rs;
+        for (int row = 0; row < nc; ++row) C[row * nc + col] = sav[two_d ? cases3[row] : row];
+    }
+    // gamma = C^-1 Sigma, Gaussian elimination with partial pivoting
+    double A[36], g[6];
+    std::memcpy(A, C, sizeof(double) * nc * nc);
+    double amax = 0.0;
+    for (int i = 0; i < nc * nc; ++i) amax = std::max(amax, std::fabs(A[i]));
+    for (int r = 0; r < nc; ++r) g[r] = S[two_d ? cases3[r] : r];
+    for (int k = 0; k < nc; ++k) {
+        int piv = k;
+        for (int r = k + 1; r < nc; ++r)
+            if (std::fabs(A[r * nc + k]) > std::fabs(A[piv * nc + k])) piv = r;
+        if (!(std::fabs(A[piv * nc + k]) > 1e-14 * amax)) return RPM_SINGULAR;
+        if (piv != k) {
+            for (int j = 0; j < nc; ++j) std::swap(A[k * nc + j], A[piv * nc + j]);
+            std::swap(g[k], g[piv]);
+        }
+        for (int r = k + 1; r < nc; ++r) {
+            const double f = A[r * nc + k] / A[k * nc + k];
+            for (int j = k; j < nc; ++j) A[r * nc + j] -= f * A[k * nc + j];
+            g[r] -= f * g[k];
+        }
+    }
+    for (int r = nc - 1; r >= 0; --r) {
+        double v = g[r];
+        for (int j = r + 1; j < nc; ++j) v -= A[r * nc + j] * g[j];
+        g[r] = v / A[r * nc + r];
+    }
+    double E[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < nc; ++r) {
+        const int i = two_d ? cases3[r] : r;
+        E[i] = i < 3 ? g[r] : 0.5 * g[r];  // tensor shear = engineering / 2
+    }
+    if (E_out) std::memcpy(E_out, E, sizeof(E));
+    c.prof.reset();
+    rs = solve_full<T>(c, pr, E, o, nullptr, (T*)eps_out, (T*)sig_out, sig_avg, st ? st + nc : nullptr, true);
+    if (rs < 0) return rs;
+    return worst != RPM_OK ? worst : rs;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1304,6 +1372,19 @@ rpm_status rpm_fft_seed_basis(const rpm_problem* pr, const rpm_options* o, const
     if (p0 < 0 || (p0 > 0 && !V) || o->scheme != RPM_SCHEME_RPM) return RPM_E_INVALID;
     if (o->precision == RPM_FP64) return seed_typed<double>(pr, o, V, p0, p_out, workspace, ws_bytes, hip_stream);
     return seed_typed<float>(pr, o, V, p0, p_out, workspace, ws_bytes, hip_stream);
+}
+
+rpm_status rpm_fft_solve_stress(const rpm_problem* pr, const double Sigma[6], const rpm_options* o, void* eps_out,
+                                void* sig_out, double sig_avg[6], double E_out[6], rpm_stats* st, void* workspace,
+                                size_t ws_bytes, void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (!Sigma || !finite6(Sigma)) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64)
+        return stress_typed<double>(pr, Sigma, o, eps_out, sig_out, sig_avg, E_out, st, workspace, ws_bytes,
+                                    hip_stream);
+    return stress_typed<float>(pr, Sigma, o, eps_out, sig_out, sig_avg, E_out, st, workspace, ws_bytes, hip_stream);
 }
 
 rpm_status rpm_workspace_basis_dim(const void* workspace, size_t ws_bytes, int32_t* p, void* hip_stream)

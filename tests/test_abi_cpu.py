@@ -163,6 +163,21 @@ def test_seed_basis_rejects_bad_arguments(B):
     assert p.value == -7  # untouched
 
 
+def test_solve_stress_rejects_bad_arguments(B):
+    lib = B._lib
+    pr = _raw_problem(B)
+    o = B.make_options()
+    S = (ctypes.c_double * 6)(0.01, 0, 0, float("nan"), 0, 0)
+    assert lib.rpm_fft_solve_stress(ctypes.byref(pr), S, ctypes.byref(o), None, None, None, None, None, 0x2000,
+                                    1 << 40, None) == -1
+    assert lib.rpm_fft_solve_stress(ctypes.byref(pr), None, ctypes.byref(o), None, None, None, None, None, 0x2000,
+                                    1 << 40, None) == -1
+    S[3] = 0.0
+    o.tol = -1.0
+    assert lib.rpm_fft_solve_stress(ctypes.byref(pr), S, ctypes.byref(o), None, None, None, None, None, 0x2000,
+                                    1 << 40, None) == -1
+
+
 def test_apply_rejects_aliasing_and_nulls(B):
     lib = B._lib
     o = B.make_options()

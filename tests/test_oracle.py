@@ -425,6 +425,53 @@ def test_seed_basis_complete_space_one_newton_step():
     np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
 
 
+# ------------------------------------------- prescribed mean stress (Sec. 2, "strain or stress")
+
+def test_stress_control_homogeneous():
+    """One phase: the strain is uniform, C^-1 Sigma (Mandel inverse), and <sigma> = Sigma."""
+    shape = (2, 4, 6)
+    ph = np.zeros(shape, dtype=np.uint8)
+    lam, mu = CF.lame(3.0, 0.3)
+    S = np.array([0.02, -0.01, 0.005, 0.003, -0.002, 0.004])
+    r = O.solve_stress(ph, np.array([[lam, mu]]), CF.lame(2.0, 0.3), S, scheme="rpm", tol=1e-12)
+    assert r["status"] == "converged"
+    w = np.sqrt(np.array([1, 1, 1, 2, 2, 2.0]))
+    em = np.linalg.solve(CF.iso_mandel(lam, mu), S * w) / w
+    np.testing.assert_allclose(r["E"], em, atol=1e-14)
+    np.testing.assert_allclose(r["eps"], np.broadcast_to(em[:, None, None, None], (6,) + shape), atol=1e-14)
+    np.testing.assert_allclose(r["sig_avg"], S, atol=1e-14)
+
+
+@pytest.mark.parametrize("axis,shape,layers", [
+    (2, (4, 4, 8), [0, 0, 1, 1, 1, 0, 2, 0]),
+    (1, (4, 6, 1), [0, 1, 0, 0, 1, 2]),  # 2-D
+])
+def test_stress_control_laminate_exact(axis, shape, layers):
+    """Laminate under a prescribed mean stress: the closed form's C_eff (columns from
+    unit strains) gives E* = C_eff^-1 Sigma, and its field for E* is the solution."""
+    ph = M.laminate(shape, layers, axis=axis)
+    tab = [(1.0, 0.3), (8.0, 0.25), (3.0, 0.35)]
+    lt = np.array([CF.lame(*p) for p in tab])
+    two_d = shape[2] == 1
+    idx = [0, 1, 5] if two_d else list(range(6))
+    S = np.array([0.02, -0.01, 0.005, 0.003, -0.002, 0.004])
+    Cc = np.zeros((len(idx), len(idx)))
+    for col, j in enumerate(idx):
+        Ej = np.zeros(6)
+        Ej[j] = 1.0 if j < 3 else 0.5
+        Cc[:, col] = CF.laminate_solution(ph, lt, Ej, axis)[1][idx]
+    g = np.linalg.solve(Cc, S[idx])
+    Es = np.zeros(6)
+    for r_, i in enumerate(idx):
+        Es[i] = g[r_] if i < 3 else 0.5 * g[r_]
+    ref_eps, ref_sig = CF.laminate_solution(ph, lt, Es, axis)
+    r = O.solve_stress(ph, lt, CF.lame(5.0, 0.3), S, scheme="rpm", tol=1e-13, max_iter=5000)
+    assert r["status"] == "converged"
+    np.testing.assert_allclose(r["E"], Es, atol=1e-13)
+    np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
+    np.testing.assert_allclose(r["sig_avg"][idx], S[idx], atol=1e-12)
+
+
 def test_basic_diverges_below_half_max_modulus():
     """Classical scheme: spectrum of F_u in [1 - E_max/E0, 1 - E_min/E0] (equal nu); a
     reference modulus below E_max / 2 puts an eigenvalue below -1 and the iteration
