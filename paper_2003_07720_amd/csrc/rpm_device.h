@@ -273,6 +273,49 @@ __device__ __forceinline__ cx<T>* ct_stages(cx<T>* src, cx<T>* dst, int nseq, in
     }
 }
 
+// In-place variant of the compile-time stages for at most one butterfly per
+// thread (nseq * N / R <= NT at every stage): each thread reads its inputs,
+// the block synchronises, then every thread writes its outputs into the same
+// rows.  Half the LDS of the ping-pong form (more resident blocks).
+template <typename T, int D, int N, int ST, int NS, int NT>
+__device__ __forceinline__ void ct_stages_ip(cx<T>* buf, int nseq, int ss, const cx<T>* tw, int tid)
+{
+    if constexpr (ST < ct_nst(N)) {
+        constexpr int R = ct_rad(N, ST);
+        constexpr int nb = N / R;
+        constexpr int tws = N / (NS * R);
+        const bool act = tid < nb * nseq;
+        const int s = tid / nb;
+        const int j = tid & (nb - 1);
+        cx<T> v[R];
+        if (act) {
+            const cx<T>* in = buf + s * ss;
+#pragma unroll
+            for (int q = 0; q < R; ++q) v[q] = in[lpad(j + q * nb)];
+            const int k = j & (NS - 1);
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int q = 1; q < R; ++q) {
+                    cx<T> w = tw[q * k * tws];
+                    if (D > 0) w.y = -w.y;
+                    v[q] = cmul(v[q], w);
+                }
+            }
+            dftR<T, R, D>(v);
+        }
+        __syncthreads();
+        if (act) {
+            const int k = j & (NS - 1);
+            const int o = (j - k) * R + k;
+            cx<T>* out = buf + s * ss;
+#pragma unroll
+            for (int q = 0; q < R; ++q) out[lpad(o + q * NS)] = v[q];
+        }
+        __syncthreads();
+        ct_stages_ip<T, D, N, ST + 1, NS * R, NT>(buf, nseq, ss, tw, tid);
+    }
+}
+
 // Full LDS FFT of nseq sequences (data in a; b is the ping-pong buffer).
 // Caller must __syncthreads() after filling a.  Returns the buffer that holds
 // the natural-order result; all threads are synchronised on return.

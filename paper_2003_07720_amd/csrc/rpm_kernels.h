@@ -39,6 +39,10 @@ __device__ __forceinline__ double2 nt_load(const double2* p)
     return make_double2(t.x, t.y);
 }
 
+#ifndef RPM_GIP_WPE
+#define RPM_GIP_WPE 5
+#endif
+
 struct Geo {
     int nx, ny, nz, nh;    // nh = nx/2 + 1 (half spectrum along x)
     long long N;           // voxels
@@ -121,7 +125,7 @@ struct MaxV<double> { static constexpr int v = 4; };
 // too (components 6..11 of S1), for the polarization iteration.
 // grid: nz * (ny / ty) blocks.  LDS: 2 * ty * lrow(nx) + nx complex + reduction.
 // ---------------------------------------------------------------------------
-template <typename T, bool VEC, bool POL, int NT>
+template <typename T, bool VEC, bool POL, int NT, bool IP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_xfwd(const T* __restrict__ xin, const uint8_t* __restrict__ phase,
                                                    const double* __restrict__ lame, int use_ref, double lam0,
                                                    double mu0, cx<T>* __restrict__ S1,
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int nx = g.nx, ty = g.ty, ss = lrow(nx);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
-    cx<T>* tw = B + ty * ss;
+    cx<T>* tw = IP ? B : B + ty * ss;  // IP: one buffer, transforms in place
     double* red = reinterpret_cast<double*>(tw + nx);
 
     const int nyt = g.ny / ty;
@@ -227,7 +231,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             }
         }
         __syncthreads();
-        const cx<T>* R = lds_fft<T, -1, NT>(A, B, px, ty, ss, tw);
+        const cx<T>* R;
+        if constexpr (IP) {
+            ct_stages_ip<T, -1, 128, 0, 1, NT>(A, ty, ss, tw, threadIdx.x);
+            R = A;
+        } else {
+            R = lds_fft<T, -1, NT>(A, B, px, ty, ss, tw);
+        }
         // split the packed transform into the two real-input spectra
         cx<T>* outa = S1 + (long long)(2 * q) * g.nspec;
         cx<T>* outb = S1 + (long long)(2 * q + 1) * g.nspec;
@@ -291,8 +301,8 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(const cx<T>* __restrict__ S1,
 // Software-pipelined y passes: a persistent grid walks the tiles; each thread
 // keeps its share of the next tile in registers (loads in flight during the
 // current tile's LDS transform and stores).  PT bounds tz * ny / kThreads.
-template <typename T, int D, int PT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_ypipe(const cx<T>* __restrict__ Sin, cx<T>* __restrict__ Sout, Geo g,
+template <typename T, int D, int PT, bool IP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (IP ? 5 : 4) : 2))) void k_ypipe(const cx<T>* __restrict__ Sin, cx<T>* __restrict__ Sout, Geo g,
                                                     Plan py, const cx<T>* __restrict__ twy, int ntiles,
                                                     const int* __restrict__ done)
 {
@@ -301,7 +311,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
     const int ny = g.ny, tz = g.tz, ss = lrow(ny);
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + tz * ss;
-    cx<T>* tw = B + tz * ss;
+    cx<T>* tw = IP ? B : B + tz * ss;  // IP: one buffer, transforms in place
     const int nzt = g.nz / tz;
     const int nel = tz * ny;
     for (int i = threadIdx.x; i < ny; i += kThreads) tw[i] = twy[i];
@@ -351,7 +361,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
         __syncthreads();
         const int tn = t + gridDim.x;
         if (tn < ntiles) load(tn);  // next tile in flight during the transform
-        const cx<T>* R = lds_fft<T, D>(A, B, py, tz, ss, tw);
+        const cx<T>* R;
+        if constexpr (IP) {
+            ct_stages_ip<T, D, 128, 0, 1, kThreads>(A, tz, ss, tw, threadIdx.x);
+            R = A;
+        } else {
+            R = lds_fft<T, D>(A, B, py, tz, ss, tw);
+        }
         int b = t;
         const int zt = b % nzt;
         b /= nzt;
@@ -633,8 +649,8 @@ __global__ __launch_bounds__(kThreads) void k_gamma(cx<T>* __restrict__ S, Geo g
 // tile in registers, in flight while the current tile is transformed,
 // filtered and stored.  Pencils past the last one are zero and never stored.
 // part_err gets one sum per block.
-template <typename T, bool POL>
-__global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g, Plan pr,
+template <typename T, bool POL, bool IP>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && IP && !POL ? RPM_GIP_WPE : 1))) void k_gpipe(cx<T>* __restrict__ S, Geo g, Plan pr,
                                                     const cx<T>* __restrict__ twr, double lam0, double mu0,
                                                     double alpha, double beta, int dc_mode,
                                                     const double* __restrict__ E,
@@ -651,7 +667,7 @@ __global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g
     const int ss = lrow(nrow);
     cx<T>* A0 = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B0 = A0 + NC * np * ss;
-    cx<T>* tw0 = B0 + NC * np * ss;
+    cx<T>* tw0 = IP ? B0 : B0 + NC * np * ss;  // IP: one buffer, transforms in place
     double* red = reinterpret_cast<double*>(tw0 + nrow);
 
     for (int i = threadIdx.x; i < nrow; i += kThreads) tw0[i] = twr[i];
@@ -685,7 +701,13 @@ __global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g
         __syncthreads();
         const int tn = t + gridDim.x;
         if (tn < ntiles) load(tn);  // next tile in flight during this one
-        cx<T>* R = lds_fft<T, -1>(A, B, pr, NC * np, ss, tw, threadIdx.x + opq);
+        cx<T>* R;
+        if constexpr (IP) {
+            ct_stages_ip<T, -1, 128, 0, 1, kThreads>(A, NC * np, ss, tw, threadIdx.x + opq);
+            R = A;
+        } else {
+            R = lds_fft<T, -1>(A, B, pr, NC * np, ss, tw, threadIdx.x + opq);
+        }
         const long long o = (long long)t * kThreads + threadIdx.x;
         const bool in = o < nlast;
         if (in) {
@@ -695,7 +717,13 @@ __global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g
                                         dc_mean, st);
         }
         __syncthreads();
-        const cx<T>* Q = lds_fft<T, +1>(R, R == A ? B : A, pr, 6 * np, ss, tw, threadIdx.x + opq);
+        const cx<T>* Q;
+        if constexpr (IP) {
+            ct_stages_ip<T, +1, 128, 0, 1, kThreads>(A, 6 * np, ss, tw, threadIdx.x + opq);
+            Q = A;
+        } else {
+            Q = lds_fft<T, +1>(R, R == A ? B : A, pr, 6 * np, ss, tw, threadIdx.x + opq);
+        }
         if (in) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) S[c * g.nspec + o] = Q[c * np * ss + la];
@@ -713,7 +741,7 @@ __global__ __launch_bounds__(kThreads) void k_gpipe(cx<T>* __restrict__ S, Geo g
 // are back.
 // grid: nz * (ny / ty).
 // ---------------------------------------------------------------------------
-template <typename T, bool POL, int NT>
+template <typename T, bool POL, int NT, bool IP>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_xinv(const cx<T>* __restrict__ S1, const T* __restrict__ eps,
                                                    T* __restrict__ out, int out_mode, const T* __restrict__ shift,
                                                    double* __restrict__ part_inc, Geo g, Plan px,
@@ -727,7 +755,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     const int nx = g.nx, ty = g.ty, ss = lrow(nx), nh = g.nh;
     cx<T>* A = reinterpret_cast<cx<T>*>(smem);
     cx<T>* B = A + ty * ss;
-    cx<T>* tw = B + ty * ss;
+    cx<T>* tw = IP ? B : B + ty * ss;  // IP: one buffer, transforms in place
     const int nyt = g.ny / ty;
     const int z = blockIdx.x / nyt;
     const int y0 = (blockIdx.x - z * nyt) * ty;
@@ -799,7 +827,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
                 }
             }
         }
-        const cx<T>* R = lds_fft<T, +1, NT>(A, B, px, ty, ss, tw);
+        const cx<T>* R;
+        if constexpr (IP) {
+            ct_stages_ip<T, +1, 128, 0, 1, NT>(A, ty, ss, tw, threadIdx.x);
+            R = A;
+        } else {
+            R = lds_fft<T, +1, NT>(A, B, px, ty, ss, tw);
+        }
 #pragma unroll
         for (int i = 0; i < MV; ++i) {
             const int v = threadIdx.x + i * NT;

@@ -34,7 +34,16 @@ constexpr double kFp32Stage = 1e-5;  // FP32 stage target before FP64 refinement
 #define RPM_YPIPE_BLOCKS 1024
 #endif
 constexpr bool kYPipe = RPM_YPIPE != 0;        // software-pipelined y passes
-constexpr int kYPipeBlocks = RPM_YPIPE_BLOCKS;  // persistent grid of the pipelined y passes
+#ifndef RPM_Y_INPLACE
+#define RPM_Y_INPLACE 1
+#endif
+#ifndef RPM_YIP_BLOCKS
+#define RPM_YIP_BLOCKS 1280
+#endif
+constexpr bool kYInPlace = RPM_Y_INPLACE != 0;  // in-place y transforms (half the LDS)
+// persistent grid of the pipelined y passes (four, or with in-place transforms five, resident blocks per CU)
+constexpr int kYPipeBlocks = RPM_YPIPE_BLOCKS;
+constexpr int kYipBlocks = RPM_YIP_BLOCKS;
 #ifndef RPM_TDOTS_BLOCKS
 #define RPM_TDOTS_BLOCKS 1024
 #endif
@@ -46,6 +55,18 @@ constexpr int kTdotsBlocks = RPM_TDOTS_BLOCKS;  // grid cap of the basis product
 #define RPM_GPIPE_BLOCKS 1280
 #endif
 constexpr bool kGPipe = RPM_GPIPE != 0;        // software-pipelined gamma pass
+#ifndef RPM_G_INPLACE
+#define RPM_G_INPLACE 1
+#endif
+#ifndef RPM_GIP_BLOCKS
+#define RPM_GIP_BLOCKS 1280
+#endif
+constexpr bool kGInPlace = RPM_G_INPLACE != 0;  // in-place gamma transforms
+#ifndef RPM_X_INPLACE
+#define RPM_X_INPLACE 1
+#endif
+constexpr bool kXInPlace = RPM_X_INPLACE != 0;  // in-place x transforms
+constexpr int kGipBlocks = RPM_GIP_BLOCKS;      // persistent grid with in-place transforms
 constexpr int kGPipeBlocks = RPM_GPIPE_BLOCKS;  // its persistent grid
 #ifndef RPM_X_NT
 #define RPM_X_NT 256
@@ -108,6 +129,9 @@ struct Shapes {
     int G1, Gy, Gyf, G3, Gg, Gp, Gq;  // Gyf: forward y-pass tiles (all spectral components)
     int Gt;                           // gamma tiles
     bool gpipe;                       // pipelined gamma pass (tiles of kThreads elements per component)
+    bool yip;                         // y passes transform in place (one LDS buffer)
+    bool gip;                         // gamma pass transforms in place
+    bool xip;                         // x passes transform in place
     bool ok;
 };
 
@@ -134,11 +158,16 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     while (g.ty > 1 && (size_t)(2 * g.ty * lrow(g.nx) + g.nx) * wsz + 80 * 8 > (size_t)kLdsCap)
         g.ty = largest_divisor_leq(g.ny, g.ty - 1);
     s.lds_x = (size_t)(2 * g.ty * lrow(g.nx) + g.nx) * wsz + 80 * 8;
+    // 128-point x transforms of at most one butterfly per thread run in place
+    s.xip = kXInPlace && g.nx == 128 && g.ty * 128 / 8 <= kThreads;
+    if (s.xip) s.lds_x = (size_t)(g.ty * lrow(g.nx) + g.nx) * wsz + 80 * 8;
     // y passes: tz columns of ny
     g.tz = largest_divisor_leq(g.nz, 128 / wsz);
     while (g.tz > 1 && (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz > (size_t)kLdsCap)
         g.tz = largest_divisor_leq(g.nz, g.tz - 1);
-    s.lds_y = (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz;
+    // 128-point y transforms of at most one butterfly per thread run in place
+    s.yip = kYInPlace && g.ny == 128 && g.tz * 128 / 8 <= kThreads;
+    s.lds_y = (size_t)((s.yip ? 1 : 2) * g.tz * lrow(g.ny) + g.ny) * wsz;
     // gamma pass: np pencils x ncomp components along the last axis
     const int nrow = g.two_d ? g.ny : g.nz;
     const int npen = g.two_d ? g.nh : g.ny * g.nh;
@@ -168,7 +197,10 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     s.Gyf = ncomp * g.nh * (g.nz / g.tz);
     s.Gt = (npen + g.np - 1) / g.np;
     s.gpipe = kGPipe && g.np * nrow == kThreads;
-    s.G3 = s.gpipe ? std::min(s.Gt, kGPipeBlocks) : s.Gt;  // gamma blocks (one error partial each)
+    // 128-point gamma transforms of at most one butterfly per thread run in place
+    s.gip = s.gpipe && kGInPlace && nrow == 128 && ncomp * g.np * 128 / 8 <= kThreads;
+    if (s.gip) s.lds_g = (size_t)(ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8;
+    s.G3 = s.gpipe ? std::min(s.Gt, s.gip ? kGipBlocks : kGPipeBlocks) : s.Gt;  // gamma blocks (one error partial each)
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
     s.Gp = (int)((6 * g.N + kVecBlock - 1) / kVecBlock);
     const long long ntile = (6 * g.N + kZTile - 1) / kZTile;
@@ -409,24 +441,37 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     c.mark_begin(RPM_K_XFWD, ev);
     const bool vec = g.nx % (16 / (int)sizeof(T)) == 0;
     constexpr int XT = x_threads<T>();
-#define RPM_XFWD(V, P)                                                                                         \
-    k_xfwd<T, V, P, XT><<<sh.G1, XT, sh.lds_x, c.s>>>(xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, \
-                                                      g, sh.px, c.twx(), done)
-    if (pol) {
-        if (vec) RPM_XFWD(true, true);
-        else RPM_XFWD(false, true);
+#define RPM_XFWD(V, P, I)                                                                                      \
+    k_xfwd<T, V, P, XT, I><<<sh.G1, XT, sh.lds_x, c.s>>>(xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, \
+                                                         g, sh.px, c.twx(), done)
+    if (sh.xip) {
+        if (pol) {
+            if (vec) RPM_XFWD(true, true, true);
+            else RPM_XFWD(false, true, true);
+        } else {
+            if (vec) RPM_XFWD(true, false, true);
+            else RPM_XFWD(false, false, true);
+        }
     } else {
-        if (vec) RPM_XFWD(true, false);
-        else RPM_XFWD(false, false);
+        if (pol) {
+            if (vec) RPM_XFWD(true, true, false);
+            else RPM_XFWD(false, true, false);
+        } else {
+            if (vec) RPM_XFWD(true, false, false);
+            else RPM_XFWD(false, false, false);
+        }
     }
 #undef RPM_XFWD
     c.mark_end(RPM_K_XFWD, ev, bx);
     if (!g.two_d) {
         const int tiles = pol ? sh.Gyf : sh.Gy;
         c.mark_begin(RPM_K_YFWD, ev);
-        if (kYPipe && g.tz * g.ny <= 8 * kThreads)
-            k_ypipe<T, -1, 8><<<std::min(tiles, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
-                                                                                            c.twy(), tiles, done);
+        if (kYPipe && sh.yip)
+            k_ypipe<T, -1, 8, true><<<std::min(tiles, kYipBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
+                                                                                             c.twy(), tiles, done);
+        else if (kYPipe && g.tz * g.ny <= 8 * kThreads)
+            k_ypipe<T, -1, 8, false><<<std::min(tiles, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
+                                                                                                c.twy(), tiles, done);
         else
             k_yfwd<T><<<tiles, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
         c.mark_end(RPM_K_YFWD, ev, 2.0 * (pol ? cf : 1.0) * specB);
@@ -435,9 +480,12 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     cx<T>* Sg = g.two_d ? S1 : S2;
 #define RPM_GAMMA_ARGS                                                                                    \
     Sg, g, sh.pr, c.twr(), c.lam0, c.mu0, c.alpha, c.beta, dc_mode, Edev, pmean, sh.G1, perr, c.st
-    if (sh.gpipe) {
-        if (pol) k_gpipe<T, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
-        else k_gpipe<T, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
+    if (sh.gip) {
+        if (pol) k_gpipe<T, true, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
+        else k_gpipe<T, false, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
+    } else if (sh.gpipe) {
+        if (pol) k_gpipe<T, true, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
+        else k_gpipe<T, false, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, sh.Gt, done);
     } else {
         if (pol) k_gamma<T, true><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, done);
         else k_gamma<T, false><<<sh.G3, kThreads, sh.lds_g, c.s>>>(RPM_GAMMA_ARGS, done);
@@ -446,21 +494,28 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     c.mark_end(RPM_K_GAMMA, ev, ((pol ? cf : 1.0) + 1.0) * specB);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
-        if (kYPipe && g.tz * g.ny <= 8 * kThreads)
-            k_ypipe<T, 1, 8><<<std::min(sh.Gy, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
-                                                                                          c.twy(), sh.Gy, done);
+        if (kYPipe && sh.yip)
+            k_ypipe<T, 1, 8, true><<<std::min(sh.Gy, kYipBlocks), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
+                                                                                            c.twy(), sh.Gy, done);
+        else if (kYPipe && g.tz * g.ny <= 8 * kThreads)
+            k_ypipe<T, 1, 8, false><<<std::min(sh.Gy, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
+                                                                                               c.twy(), sh.Gy, done);
         else
             k_yinv<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py, c.twy(), done);
         c.mark_end(RPM_K_YINV, ev, 2.0 * specB);
     }
     c.mark_begin(RPM_K_XINV, ev);
-    if (pol)
-        k_xinv<T, true, XT><<<sh.G1, XT, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,
-                                                          c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta, done);
-    else
-        k_xinv<T, false, XT><<<sh.G1, XT, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g,
-                                                           sh.px, c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta,
-                                                           done);
+#define RPM_XINV(P, I)                                                                                         \
+    k_xinv<T, P, XT, I><<<sh.G1, XT, sh.lds_x, c.s>>>(S1, eps_for_inv, out, out_mode, shift, part_inc, g, sh.px,     \
+                                                      c.twx(), c.phase, c.lame(), c.lam0, c.mu0, c.beta, done)
+    if (sh.xip) {
+        if (pol) RPM_XINV(true, true);
+        else RPM_XINV(false, true);
+    } else {
+        if (pol) RPM_XINV(true, false);
+        else RPM_XINV(false, false);
+    }
+#undef RPM_XINV
     c.mark_end(RPM_K_XINV, ev, bi + (pol ? (double)g.N : 0.0));
     c.check_launch();
 }
