@@ -32,11 +32,11 @@ KERNEL_SOURCES = ["include/rpmfft.h", "paper_2003_07720_amd/csrc/rpm_device.h",
                   "paper_2003_07720_amd/csrc/rpm_kernels.h", "paper_2003_07720_amd/csrc/rpm_solver.hip"]
 # kernel symbols (FP32 path) behind each timing class of rpm_stats
 CLASS_SYMBOLS = {
-    "xfwd": r"rpm::k_xfwd<float, (true|false), false(, \d+)?>",
-    "yfwd": r"rpm::k_ypipe<float, -1, \d+>|rpm::k_yfwd<float>",
-    "gamma": r"rpm::k_(gamma|gpipe)<float, false>",
-    "yinv": r"rpm::k_ypipe<float, 1, \d+>|rpm::k_yinv<float>",
-    "xinv": r"rpm::k_xinv<float, false(, \d+)?>",
+    "xfwd": r"rpm::k_xfwd<float, (true|false), false(, \d+)?(, (true|false))?>",
+    "yfwd": r"rpm::k_ypipe<float, -1, \d+(, (true|false))?>|rpm::k_yfwd<float>",
+    "gamma": r"rpm::k_(gamma|gpipe)<float, false(, (true|false))?>",
+    "yinv": r"rpm::k_ypipe<float, 1, \d+(, (true|false))?>|rpm::k_yinv<float>",
+    "xinv": r"rpm::k_xinv<float, false(, \d+)?(, (true|false))?>",
     "project": r"rpm::k_gdots<float, float, [12], 0>",
     "recombine": r"rpm::k_recombine<float>",
 }
