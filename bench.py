@@ -138,8 +138,14 @@ def parse():
 
 # Iterations and seconds printed in Table 1 (Sec. 5.5; Matlab, hardware not
 # stated): K -> (Acc-FFT, RPM-Acc-FFT iterations, Acc-FFT s, RPM-Acc-FFT s).
-TABLE1 = {500: (234, 83, 6.46, 4.47), 1000: (335, 81, 8.51, 4.42), 5000: (335, 81, 20.24, 4.40),
-          10000: (1136, 82, 28.29, 4.44), 50000: (2741, 82, 68.56, 4.45), 100000: (3863, 161, 98.60, 11.13)}
+TABLE1_FILE = os.path.join(ROOT, "tests", "golden", "table1_paper.json")
+
+
+def table1_paper():
+    """The paper's Table 1 (Sec. 5.5) as {K: (acc_iters, rpm_acc_iters, acc_s, rpm_acc_s)}."""
+    with open(TABLE1_FILE) as fh:
+        t = json.load(fh)
+    return {int(r[0]): tuple(r[1:]) for r in t["rows"]}
 
 
 def table1():
@@ -152,7 +158,7 @@ def table1():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     rows = []
-    for K, paper in TABLE1.items():
+    for K, paper in table1_paper().items():
         w = M.workload_fibre(K)
         phase = torch.from_numpy(w["phase"]).to("cuda")
         lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
@@ -231,7 +237,7 @@ def main():
         stress_bench()
         return
     if a.gpus != 1:
-        print(f"bench.py: --gpus {a.gpus} refused: this build runs on a single GPU (one process, one device); "
+        print(f"bench.py: --gpus {a.gpus} refused: the benchmark runs on a single GPU (one process, one device); "
               f"run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

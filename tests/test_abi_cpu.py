@@ -188,3 +188,15 @@ def test_apply_rejects_aliasing_and_nulls(B):
     assert lib.rpm_fft_apply(ctypes.byref(pr), E, ctypes.byref(o), None, 0x3000, None, None, 0x2000, 1 << 40,
                              None) == -1
     assert lib.rpm_fft_apply(None, E, ctypes.byref(o), 0x3000, 0x4000, None, None, 0x2000, 1 << 40, None) == -1
+
+
+def test_table1_fixture():
+    """The stored Table 1 of Sec. 5.5 (context for the contrast sweep): six contrasts,
+    RPM around the Accelerated FFT needing fewer iterations and less time at each."""
+    import bench
+
+    t = bench.table1_paper()
+    assert sorted(t) == [500, 1000, 5000, 10000, 50000, 100000]
+    for K, (acc_it, rpm_it, acc_s, rpm_s) in t.items():
+        assert rpm_it < acc_it and rpm_s < acc_s
+    assert t[10000] == (1136, 82, 28.29, 4.44)
