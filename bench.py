@@ -332,6 +332,29 @@ def main():
                                                  seconds=round(u1 - u0, 4), residual=r3["residual"])
         ttt_info["looser_tolerances"] = loose
         print(f"bench: looser tolerances {loose}", file=sys.stderr, flush=True)
+        # warm start (eps0) from the same cell on the half-resolution grid (the
+        # phase of every second voxel), solved to the same tolerance, its strain
+        # repeated over 2 x 2 x 2 voxels; the time includes the coarse solve
+        warm = {}
+        ph_c = phase[::2, ::2, ::2].contiguous()
+        o_c = B.make_options(max_iter=a.ttt_iters, **dict(common, refine=0))
+        ws_c = B.make_workspace(tuple(ph_c.shape), o_c)
+        for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
+            o4 = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, refine=0))
+            torch.cuda.synchronize()
+            v0 = time.perf_counter()
+            rc = B.fft_solve(ph_c, lt, l0, E, o4, workspace=ws_c)
+            e0 = rc["eps"]
+            for d in (1, 2, 3):
+                e0 = e0.repeat_interleave(2, dim=d)
+            rf = B.fft_solve(phase, lt, l0, E, o4, eps0=e0.contiguous(), workspace=ws, want_eps=False)
+            torch.cuda.synchronize()
+            v1 = time.perf_counter()
+            warm[f"rpm@{tl:g}"] = dict(status=rf["status"], iterations=rf["iterations"],
+                                       coarse_iterations=rc["iterations"], seconds=round(v1 - v0, 4),
+                                       residual=rf["residual"])
+        ttt_info["coarse_grid_warm_start"] = warm
+        print(f"bench: coarse-grid warm start {warm}", file=sys.stderr, flush=True)
 
     # CPU oracle on a bounded sample of the same workload
     cpu = None
