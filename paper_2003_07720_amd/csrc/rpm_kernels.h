@@ -1032,8 +1032,8 @@ __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, co
     }
 }
 
-// SITE separates the call sites (0: the per-step projections, 1: basis
-// growth); the per-step stream reads the basis with non-temporal loads.
+// SITE separates the call sites in profiles (0: the per-step projections, 1:
+// basis growth); both read the basis with non-temporal loads.
 template <typename TA, typename TZ, int NF, int SITE>
 __global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restrict__ Z, int p, int zP, long long N,
                                                double* __restrict__ part, int ld)
@@ -1052,10 +1052,10 @@ __global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restric
         for (int u = 0; u < 8; ++u) acc[f][u] = 0.0;
     long long tile = blockIdx.x;
     for (; tile < nfull; tile += gridDim.x)
-        gdots_tile<true, TA, TZ, NF, SITE == 0>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+        gdots_tile<true, TA, TZ, NF, true>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
                                      tile * kZTile + lo, L6, N3, acc);
     if (tile == nfull && nfull * kZTile < L6)  // the last, partial tile
-        gdots_tile<false, TA, TZ, NF, SITE == 0>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+        gdots_tile<false, TA, TZ, NF, true>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
                                       tile * kZTile + lo, L6, N3, acc);
 #pragma unroll
     for (int f = 0; f < NF; ++f)
@@ -1558,7 +1558,7 @@ __global__ __launch_bounds__(kThreads) void k_growth_diff(const T* __restrict__ 
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const T* zc_ = zt + (long long)min(g + u, p - 1) * kZTile;
-                if (full) raw[u].load(zc_);
+                if (full) raw[u].template load_s<true>(zc_);
                 else raw[u].load_tail(zc_, e0, L6);
             }
 #pragma unroll
