@@ -106,7 +106,12 @@ typedef struct {
     int32_t scheme;           /* RPM_SCHEME_BASIC or RPM_SCHEME_RPM              */
     int32_t precision;        /* RPM_FP64 or RPM_FP32                            */
     int32_t reuse_basis;      /* keep Z, W, H left in the workspace by the
-                                 previous call on the same grid and precision   */
+                                 previous call on the same grid, precision,
+                                 p_max and map (else start from an empty basis;
+                                 max_iter may differ).  The basis holds the
+                                 linear part of that call's map: reuse it only
+                                 with the same phase map, phase table and
+                                 reference medium                               */
     int32_t check_every;      /* host reads the convergence flag every this many
                                  iterations (>= 1); iterations queued after
                                  convergence do nothing                          */

@@ -70,14 +70,14 @@ __host__ __device__ __forceinline__ long long zix(long long e, int j, int P)
 // Device-resident solver state (one per workspace).
 struct DevState {
     int magic;         // kStateMagic once the workspace has been initialised
-    int cfg[5];        // nx, ny, nz, precision, p_max the basis was built for
+    int cfg[6];        // nx, ny, nz, precision, p_max, map the basis was built for
     int done;          // 1 once the iteration stopped (any reason)
     int status;        // 0 converged, 1 not converged, 2 diverged, 3 singular
     int iters;         // main-loop F applications so far
     int p;             // basis dimension
     int singular;      // LU of I - H hit a tiny pivot
     int max_iter;
-    int pad0, pad1;
+    int pad1;
     double tol;
     double err0;       // error of the starting iterate
     double err;        // error of the latest iterate

@@ -257,7 +257,6 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.twy = take(sizeof(cx<T>) * kMaxN);
     L.twr = take(sizeof(cx<T>) * kMaxN);
     L.lame = take(sizeof(double) * 512);
-    L.hist = take(sizeof(double) * L.hist_cap);
     L.pmean = take(sizeof(double) * 6 * s.G1);
     L.perr = take(sizeof(double) * s.G3);
     L.pinc = take(sizeof(double) * s.G1);
@@ -290,6 +289,9 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
         const rpm_options b = basic_fp64_options(o);
         off = align_up(off + make_layout<double>(make_shapes<double>(n, spectral_comps(&b)), &b).total);
     }
+    // last: its size follows max_iter, which may differ between calls that
+    // carry the basis, so nothing the workspace keeps may sit behind it
+    L.hist = take(sizeof(double) * L.hist_cap);
     L.total = off;
     return L;
 }
@@ -606,7 +608,7 @@ rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool 
     DevState hs;
     if (hipMemcpyAsync(&hs, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.s) != hipSuccess) return RPM_E_HIP;
     if (hipStreamSynchronize(c.s) != hipSuccess) return RPM_E_HIP;
-    const int cfg[5] = {g.nx, g.ny, g.nz, o->precision, c.pmax};
+    const int cfg[6] = {g.nx, g.ny, g.nz, o->precision, c.pmax, o->map};
     bool same = hs.magic == kStateMagic && std::memcmp(hs.cfg, cfg, sizeof(cfg)) == 0;
     if (!(same && want_reuse)) {
         std::memset(&hs, 0, sizeof(hs));
