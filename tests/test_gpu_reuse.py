@@ -71,3 +71,29 @@ def test_basis_carried_between_solves_fp64(B, caps, loads):
     # (I - H)^-1, which amplifies the rounding of the two sides' different
     # summation orders in the relative error of each entry
     np.testing.assert_allclose(gb["history"], rb["history"], rtol=1e-6, atol=1e-10 * rb["history"][0])
+
+
+def test_basis_carried_between_solves_fp32(B):
+    """FP32 fields: the basis of an xx solve (cap 400) kept for a zz solve (cap
+    1500) reaches the FP64-certified tolerance and the oracle's solution (FP32
+    certification bar: 1e-4 relative in the field)."""
+    import torch
+
+    print("reuse between solves fp32", flush=True)
+    ph, _ = M.rsa_spheres(16, 2.0, 3.0, 0.1, seed=9)
+    lt = O.lame_table(PHASES)
+    l0 = O.lame(10.5, 0.3)
+    ref = O.solve(ph, lt, l0, EZZ, scheme="rpm", tol=1e-10, max_iter=3000, n_max=10, p_max=32)
+    assert ref["status"] == "converged"
+    glt = np.array([B.lame_from_young(*p) for p in PHASES])
+    gl0 = B.lame_from_young(10.5, 0.3)
+    gph = torch.from_numpy(ph).to("cuda")
+    common = dict(scheme="rpm", precision="fp32", tol=1e-6, n_max=10, p_max=32)
+    ws = B.make_workspace(ph.shape, B.make_options(max_iter=1500, **common))
+    ga = B.fft_solve(gph, glt, gl0, EXX, B.make_options(max_iter=400, **common), workspace=ws, want_eps=False)
+    assert ga["status"] == "RPM_OK" and ga["basis_dim"] > 0
+    gb = B.fft_solve(gph, glt, gl0, EZZ, B.make_options(max_iter=1500, reuse_basis=1, **common), workspace=ws)
+    assert gb["status"] == "RPM_OK" and gb["residual_fp64"] <= 1e-6
+    assert gb["basis_dim"] >= ga["basis_dim"]
+    eps = gb["eps"].cpu().numpy().astype(np.float64)
+    assert np.abs(eps - ref["eps"]).max() <= 1e-4 * np.abs(ref["eps"]).max()
