@@ -73,6 +73,12 @@ def test_workspace_size_rules(B):
     assert B.workspace_size((32, 32, 32), B.make_options(precision="fp32")) < B.workspace_size((32, 32, 32), o)
     with pytest.raises(B.RpmError):
         B.workspace_size((8, 8, 8), B.make_options(p_max=65))
+    # only the error history (one double per main-loop F call) follows max_iter,
+    # so calls that carry the basis may take different caps
+    for prec in ("fp64", "fp32"):
+        a = B.workspace_size((32, 32, 32), B.make_options(precision=prec, max_iter=1000))
+        b = B.workspace_size((32, 32, 32), B.make_options(precision=prec, max_iter=1000 + 4096))
+        assert b - a == 8 * 4096
     # the polarization iteration carries eps through the forward passes: twice the spectra
     sp = B.workspace_size((32, 32, 32), B.make_options(map="polarization"))
     assert sp >= B.workspace_size((32, 32, 32), o) + 2 * 6 * 17 * 32 * 32 * 16
