@@ -86,6 +86,7 @@ struct DevState {
     double E[6];       // prescribed mean strain of the current solve
     double Ezero[6];   // zeros (mean strain of Jacobian-vector products)
     double gnorm;      // norm of the shift field of a correction solve
+    double medium[6];  // lambda0, mu0, alpha, beta and a hash of the phase table the basis was built for
     double z[kMaxP], zeta[kMaxP], d[kMaxP];
     double zeta_ring[4][kMaxP];
     double H[kMaxP * kMaxP];

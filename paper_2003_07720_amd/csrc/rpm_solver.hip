@@ -609,11 +609,28 @@ rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool 
     if (hipMemcpyAsync(&hs, c.st, sizeof(DevState), hipMemcpyDeviceToHost, c.s) != hipSuccess) return RPM_E_HIP;
     if (hipStreamSynchronize(c.s) != hipSuccess) return RPM_E_HIP;
     const int cfg[6] = {g.nx, g.ny, g.nz, o->precision, c.pmax, o->map};
-    bool same = hs.magic == kStateMagic && std::memcmp(hs.cfg, cfg, sizeof(cfg)) == 0;
+    // the basis holds the linear part of the map: it depends on the reference
+    // medium, the polarization parameters and the phase table (FNV-1a over
+    // the table's bytes, kept as two 32-bit halves)
+    uint64_t h = 1469598103934665603ull;
+    for (int i = 0; i < 2 * pr->n_phases; ++i) {
+        uint64_t b;
+        std::memcpy(&b, &pr->lame[i], sizeof(b));
+        for (int k = 0; k < 8; ++k) {
+            h ^= (b >> (8 * k)) & 0xffu;
+            h *= 1099511628211ull;
+        }
+    }
+    const bool pol = o->map == RPM_MAP_POLARIZATION;
+    const double medium[6] = {c.lam0, c.mu0, pol ? o->alpha : 0.0, pol ? o->beta : 0.0,
+                              (double)(uint32_t)(h >> 32), (double)(uint32_t)h};
+    bool same = hs.magic == kStateMagic && std::memcmp(hs.cfg, cfg, sizeof(cfg)) == 0 &&
+                std::memcmp(hs.medium, medium, sizeof(medium)) == 0;
     if (!(same && want_reuse)) {
         std::memset(&hs, 0, sizeof(hs));
         hs.magic = kStateMagic;
         std::memcpy(hs.cfg, cfg, sizeof(cfg));
+        std::memcpy(hs.medium, medium, sizeof(medium));
         hs.p = 0;
     }
     hs.done = 0;

@@ -97,3 +97,30 @@ def test_basis_carried_between_solves_fp32(B):
     assert gb["basis_dim"] >= ga["basis_dim"]
     eps = gb["eps"].cpu().numpy().astype(np.float64)
     assert np.abs(eps - ref["eps"]).max() <= 1e-4 * np.abs(ref["eps"]).max()
+
+
+@pytest.mark.parametrize("change", ["medium", "table"])
+def test_reuse_with_another_map_starts_empty(B, change):
+    """A reuse call whose map differs from the one the kept basis was built for
+    (another reference medium, or another phase table) starts from an empty
+    basis: it follows the solve in a fresh workspace step by step."""
+    import torch
+
+    print(f"reuse with another {change}", flush=True)
+    ph, _ = M.rsa_spheres(16, 2.0, 3.0, 0.1, seed=9)
+    gph = torch.from_numpy(ph).to("cuda")
+    lt_a = np.array([B.lame_from_young(*p) for p in PHASES])
+    lt_b = np.array([B.lame_from_young(*p) for p in ([(1.0, 0.3), (15.0, 0.3)] if change == "table" else PHASES)])
+    l0_a = B.lame_from_young(10.5, 0.3)
+    l0_b = B.lame_from_young(12.0 if change == "medium" else 10.5, 0.3)
+    common = dict(scheme="rpm", precision="fp64", tol=1e-8, n_max=10, p_max=32, max_iter=1000)
+    ws = B.make_workspace(ph.shape, B.make_options(**common))
+    ga = B.fft_solve(gph, lt_a, l0_a, EXX, B.make_options(**common), workspace=ws, want_eps=False)
+    assert ga["status"] == "RPM_OK" and ga["basis_dim"] > 0
+    gb = B.fft_solve(gph, lt_b, l0_b, EZZ, B.make_options(reuse_basis=1, **common), workspace=ws)
+    ws2 = B.make_workspace(ph.shape, B.make_options(**common))
+    gf = B.fft_solve(gph, lt_b, l0_b, EZZ, B.make_options(**common), workspace=ws2)
+    assert gb["status"] == gf["status"] == "RPM_OK"
+    assert gb["iterations"] == gf["iterations"] and gb["basis_dim"] == gf["basis_dim"]
+    np.testing.assert_allclose(gb["history"], gf["history"], rtol=1e-12, atol=0)
+    assert torch.equal(gb["eps"], gf["eps"])
