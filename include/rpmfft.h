@@ -109,9 +109,10 @@ typedef struct {
                                  previous call on the same grid, precision,
                                  p_max and map (else start from an empty basis;
                                  max_iter may differ).  The basis holds the
-                                 linear part of that call's map: reuse it only
-                                 with the same phase map, phase table and
-                                 reference medium                               */
+                                 linear part of that call's map: a call with
+                                 another reference medium, phase table or
+                                 alpha/beta also starts from an empty basis;
+                                 the phase map is not checked (keep it)         */
     int32_t check_every;      /* host reads the convergence flag every this many
                                  iterations (>= 1); iterations queued after
                                  convergence do nothing                          */
