@@ -66,7 +66,9 @@ typedef enum {
     RPM_E_INVALID = -1,         /* bad argument (null pointer, range, NaN ...)   */
     RPM_E_UNSUPPORTED_SIZE = -2,/* an extent is not a 2,3-smooth size <= 512     */
     RPM_E_WORKSPACE = -3,       /* workspace missing or smaller than required    */
-    RPM_E_HIP = -5              /* a HIP runtime call failed                     */
+    RPM_E_HIP = -5,             /* a HIP runtime call failed                     */
+    RPM_E_SCRATCH = -6          /* rpm_fft_apply_static: the grid needs more than
+                                   the library's static device scratch          */
 } rpm_status;
 
 enum { RPM_SCHEME_BASIC = 0, /* Algorithm 1: eps <- F(eps)                       */
@@ -260,6 +262,26 @@ rpm_status rpm_fft_seed_basis(const rpm_problem *pr, const rpm_options *o, const
 rpm_status rpm_fft_solve_stress(const rpm_problem *pr, const double Sigma[6], const rpm_options *o, void *eps_out,
                                 void *sig_out, double sig_avg[6], double E_out[6], rpm_stats *st, void *workspace,
                                 size_t ws_bytes, void *hip_stream);
+
+/*
+ * rpm_fft_apply without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same map application, the same kernels and launch
+ * shapes, with the scratch (spectra, partial sums, solver state) taken from a
+ * static device array of RPM_STATIC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends.  Calls no hipMalloc/hipFree.
+ *   eps, xi   DEVICE fields in o->precision on the CURRENT device, whose stream
+ *             hip_stream must be (may not alias).
+ *   err, sig_avg  HOST nullable, as rpm_fft_apply.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (the state it needs is re-initialised on every call): calls that
+ * overlap on one GPU, on any streams, race.  Returns RPM_E_SCRATCH, before any
+ * device work, when the grid needs more scratch than the array holds (128^3
+ * FP32 fits; 128^3 FP64 does not); other errors as rpm_fft_apply.
+ */
+#define RPM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+rpm_status rpm_fft_apply_static(const rpm_problem *pr, const double E[6], const rpm_options *o, const void *eps,
+                                void *xi, double *err, double sig_avg[6], void *hip_stream);
 
 /* Current basis dimension stored in a workspace (0 if never used).  HOST p. */
 rpm_status rpm_workspace_basis_dim(const void *workspace, size_t ws_bytes, int32_t *p, void *hip_stream);

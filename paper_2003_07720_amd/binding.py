@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 RPM_NKERNEL = 10
 KERNEL_NAMES = ["xfwd", "yfwd", "gamma", "yinv", "xinv", "reduce", "finalize", "growth", "project", "recombine"]
 STATUS = {0: "RPM_OK", 1: "RPM_NOT_CONVERGED", 2: "RPM_DIVERGED", 3: "RPM_SINGULAR", -1: "RPM_E_INVALID",
-          -2: "RPM_E_UNSUPPORTED_SIZE", -3: "RPM_E_WORKSPACE", -5: "RPM_E_HIP"}
+          -2: "RPM_E_UNSUPPORTED_SIZE", -3: "RPM_E_WORKSPACE", -5: "RPM_E_HIP", -6: "RPM_E_SCRATCH"}
 SCHEME = {"basic": 0, "rpm": 1}
 MAP = {"classical": 0, "polarization": 1}
 PRECISION = {"fp64": 0, "fp32": 1}
@@ -64,6 +64,7 @@ _lib.rpm_default_options.restype = None
 _lib.rpm_lame_from_young.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp]
 _lib.rpm_workspace_size.argtypes = [_P(ctypes.c_int32), _P(RpmOptions), _P(ctypes.c_size_t)]
 _lib.rpm_fft_apply.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _dp, _dp, _vp, ctypes.c_size_t, _vp]
+_lib.rpm_fft_apply_static.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _dp, _dp, _vp]
 _lib.rpm_fft_solve.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, _vp, _vp, _dp, _P(RpmStats), _vp,
                                ctypes.c_size_t, _vp]
 _lib.rpm_fft_effective_tensor.argtypes = [_P(RpmProblem), _P(RpmOptions), _dp, _P(RpmStats), _vp, ctypes.c_size_t,
@@ -75,11 +76,12 @@ _lib.rpm_fft_seed_basis.argtypes = [_P(RpmProblem), _P(RpmOptions), _vp, ctypes.
                                     ctypes.c_size_t, _vp]
 _lib.rpm_status_string.argtypes = [ctypes.c_int]
 _lib.rpm_status_string.restype = ctypes.c_char_p
-for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve", "rpm_fft_effective_tensor",
+for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_apply_static", "rpm_fft_solve", "rpm_fft_effective_tensor",
            "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_solve",
+EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply",
+            "rpm_fft_apply_static", "rpm_fft_solve",
             "rpm_fft_effective_tensor", "rpm_fft_solve_stress", "rpm_fft_seed_basis", "rpm_workspace_basis_dim",
             "rpm_status_string"]
 
@@ -185,6 +187,26 @@ def fft_apply(phase, lame_tab, lame0, E, eps, opts=None, workspace=None):
                             ctypes.byref(err), sav, ws.data_ptr(), ws.numel(), _stream())
     if rc != 0:
         raise RpmError(rc, "rpm_fft_apply")
+    return xi, err.value, np.array(sav[:])
+
+
+def fft_apply_static(phase, lame_tab, lame0, E, eps, opts=None, xi=None):
+    """fft_apply without a workspace: the library's static device scratch serves
+    the call (rpm_fft_apply_static).  xi (nullable) is the caller's output."""
+    opts = opts or make_options()
+    shape = tuple(phase.shape)
+    _check_field(eps, shape, field_dtype(opts), "eps")
+    if xi is None:
+        xi = torch.empty_like(eps)
+    _check_field(xi, shape, field_dtype(opts), "xi")
+    pr = _problem(phase, lame_tab, lame0)
+    Ea = (ctypes.c_double * 6)(*[float(x) for x in E])
+    err = ctypes.c_double()
+    sav = (ctypes.c_double * 6)()
+    rc = _lib.rpm_fft_apply_static(ctypes.byref(pr), Ea, ctypes.byref(opts), eps.data_ptr(), xi.data_ptr(),
+                                   ctypes.byref(err), sav, _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fft_apply_static")
     return xi, err.value, np.array(sav[:])
 
 

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "rpm_kernels.h"
@@ -233,19 +234,21 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp);
 int spectral_comps(const rpm_options* o) { return o->map == RPM_MAP_POLARIZATION ? 12 : 6; }
 
 template <typename T>
-Layout make_layout(const Shapes<T>& s, const rpm_options* o);
+Layout make_layout(const Shapes<T>& s, const rpm_options* o, bool map_only = false);
 
+// Workspace layout.  map_only: what one map application needs (state, tables,
+// partial sums, spectra), no fields, basis or FP64 sub-pipeline.
 template <typename T>
-Layout make_layout(const Shapes<T>& s, const rpm_options* o)
+Layout make_layout(const Shapes<T>& s, const rpm_options* o, bool map_only)
 {
     Layout L{};
     const Geo& g = s.g;
-    const size_t fT = (size_t)6 * g.N * sizeof(T);
+    const size_t fT = map_only ? 0 : (size_t)6 * g.N * sizeof(T);
     const size_t fD = (size_t)6 * g.N * sizeof(double);
     const size_t spec = (size_t)g.ncomp * g.nspec * sizeof(cx<T>);
-    const int pmax = o->scheme == RPM_SCHEME_RPM ? o->p_max : 0;
+    const int pmax = (o->scheme == RPM_SCHEME_RPM && !map_only) ? o->p_max : 0;
     L.ld = kMaxP;
-    L.hist_cap = (long long)o->max_iter + 1;
+    L.hist_cap = map_only ? 2 : (long long)o->max_iter + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         size_t at = off;
@@ -281,7 +284,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o)
     L.D0 = take(pmax > 0 ? fD : 0);
     // FP32 fields: shift field of the correction solves and an FP64 pipeline
     // for certification and refinement
-    const bool fp32 = sizeof(T) == 4;
+    const bool fp32 = sizeof(T) == 4 && !map_only;
     L.shift = take(fp32 ? fT : 0);
     L.sub64 = off;
     if (fp32) {
@@ -1133,13 +1136,15 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
 
 template <typename T>
 rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void* ws, size_t ws_bytes,
-                    void* stream)
+                    void* stream, bool map_only = false)
 {
     c.sh = make_shapes<T>(pr->n, spectral_comps(o));
     if (!c.sh.ok) return RPM_E_UNSUPPORTED_SIZE;
     // FP32 fields are certified by an FP64 pipeline on the same grid
-    if (sizeof(T) == 4 && !make_shapes<double>(pr->n, spectral_comps(o)).ok) return RPM_E_UNSUPPORTED_SIZE;
-    c.L = make_layout<T>(c.sh, o);
+    if (sizeof(T) == 4 && !map_only && !make_shapes<double>(pr->n, spectral_comps(o)).ok)
+        return RPM_E_UNSUPPORTED_SIZE;
+    c.L = make_layout<T>(c.sh, o, map_only);
+    if (map_only && c.L.total > ws_bytes) return RPM_E_SCRATCH;
     if (!ws || ws_bytes < c.L.total) return RPM_E_WORKSPACE;
     if (!pr->phase) return RPM_E_INVALID;
     c.s = (hipStream_t)stream;
@@ -1148,7 +1153,7 @@ rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void
     c.phase = pr->phase;
     c.lam0 = pr->lame0[0];
     c.mu0 = pr->lame0[1];
-    c.pmax = o->scheme == RPM_SCHEME_RPM ? o->p_max : 0;
+    c.pmax = (o->scheme == RPM_SCHEME_RPM && !map_only) ? o->p_max : 0;
     c.pol = o->map == RPM_MAP_POLARIZATION;
     c.alpha = o->alpha;
     c.beta = o->beta;
@@ -1177,10 +1182,10 @@ rpm_status solve_typed(const rpm_problem* pr, const double E[6], const rpm_optio
 
 template <typename T>
 rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps, void* xi,
-                       double* err, double* sig_avg, void* ws, size_t ws_bytes, void* stream)
+                       double* err, double* sig_avg, void* ws, size_t ws_bytes, void* stream, bool map_only = false)
 {
     Ctx<T> c;
-    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream, map_only);
     if (rs != RPM_OK) return rs;
     int p = 0;
     rs = prepare(c, pr, o, false, &p, o->tol);
@@ -1346,6 +1351,32 @@ rpm_status stress_typed(const rpm_problem* pr, const double S[6], const rpm_opti
     return worst != RPM_OK ? worst : rs;
 }
 
+// Scratch of rpm_fft_apply_static: one copy per GPU (each device holds its own
+// instance of this array at its own address), kept until the process ends.
+// Host code never uses the array's name as a device address: the address of
+// the current device's copy comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[RPM_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device, with it current).
+rpm_status static_scratch(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return RPM_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RPM_E_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RPM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1416,6 +1447,37 @@ rpm_status rpm_fft_apply(const rpm_problem* pr, const double E[6], const rpm_opt
     return apply_typed<float>(pr, E, o, eps, xi, err, sig_avg, workspace, ws_bytes, hip_stream);
 }
 
+rpm_status rpm_fft_apply_static(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps,
+                                void* xi, double* err, double sig_avg[6], void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (!E || !finite6(E) || !eps || !xi || eps == xi) return RPM_E_INVALID;
+    // the size check needs no device: reject before touching the scratch
+    {
+        rpm_options b = *o;
+        b.scheme = RPM_SCHEME_BASIC;
+        size_t need = 0;
+        if (o->precision == RPM_FP64) {
+            Shapes<double> s = make_shapes<double>(pr->n, spectral_comps(o));
+            if (!s.ok) return RPM_E_UNSUPPORTED_SIZE;
+            need = make_layout<double>(s, &b, true).total;
+        } else {
+            Shapes<float> s = make_shapes<float>(pr->n, spectral_comps(o));
+            if (!s.ok) return RPM_E_UNSUPPORTED_SIZE;
+            need = make_layout<float>(s, &b, true).total;
+        }
+        if (need > RPM_STATIC_SCRATCH_BYTES) return RPM_E_SCRATCH;
+    }
+    void* ws = nullptr;
+    if ((rs = static_scratch(&ws)) != RPM_OK) return rs;
+    rpm_options b = *o;
+    b.profile = 0;  // no event objects either
+    if (o->precision == RPM_FP64)
+        return apply_typed<double>(pr, E, &b, eps, xi, err, sig_avg, ws, RPM_STATIC_SCRATCH_BYTES, hip_stream, true);
+    return apply_typed<float>(pr, E, &b, eps, xi, err, sig_avg, ws, RPM_STATIC_SCRATCH_BYTES, hip_stream, true);
+}
+
 rpm_status rpm_fft_solve(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps0,
                          void* eps_out, void* sig_out, double sig_avg[6], rpm_stats* st, void* workspace,
                          size_t ws_bytes, void* hip_stream)
@@ -1484,6 +1546,7 @@ const char* rpm_status_string(rpm_status s)
         case RPM_E_UNSUPPORTED_SIZE: return "RPM_E_UNSUPPORTED_SIZE";
         case RPM_E_WORKSPACE: return "RPM_E_WORKSPACE";
         case RPM_E_HIP: return "RPM_E_HIP";
+        case RPM_E_SCRATCH: return "RPM_E_SCRATCH";
     }
     return "RPM_UNKNOWN";
 }

@@ -206,3 +206,25 @@ def test_table1_fixture():
     for K, (acc_it, rpm_it, acc_s, rpm_s) in t.items():
         assert rpm_it < acc_it and rpm_s < acc_s
     assert t[10000] == (1136, 82, 28.29, 4.44)
+
+
+def test_apply_static_rejects_before_device_work(B):
+    """The allocation-free map application refuses, with no device work, grids
+    that need more than its static scratch, and the same bad arguments as
+    rpm_fft_apply."""
+    lib = B._lib
+    pr = _raw_problem(B)
+    E = (ctypes.c_double * 6)(0.01, 0, 0, 0, 0, 0)
+    o = B.make_options(precision="fp64")
+    assert lib.rpm_fft_apply_static(ctypes.byref(pr), E, ctypes.byref(o), 0x3000, 0x3000, None, None, None) == -1
+    assert lib.rpm_fft_apply_static(ctypes.byref(pr), E, ctypes.byref(o), None, 0x3000, None, None, None) == -1
+    big = _raw_problem(B)
+    big.n[0], big.n[1], big.n[2] = 256, 256, 256
+    for prec in ("fp64", "fp32"):
+        o = B.make_options(precision=prec)
+        assert lib.rpm_fft_apply_static(ctypes.byref(big), E, ctypes.byref(o), 0x3000, 0x4000, None, None,
+                                        None) == -6
+    big.n[0], big.n[1], big.n[2] = 128, 128, 128
+    o = B.make_options(precision="fp64")  # 128^3 spectra in FP64 exceed the array
+    assert lib.rpm_fft_apply_static(ctypes.byref(big), E, ctypes.byref(o), 0x3000, 0x4000, None, None, None) == -6
+    assert B.status_string(-6) == "RPM_E_SCRATCH"
