@@ -1,12 +1,15 @@
 """Benchmark: voxel-iterations/s and time to a 1e-6 equilibrium error of RPM-FFT
 on the 128^3 void cell (30 % spherical voids of stiffness 1e-8, matrix E = 1,
 nu = 0.3, mean strain eps_zz = 0.01), FP32 fields and FFTs with FP64 RPM steps,
-basis capped at 32, n_max = 10.
+basis capped at 32, n_max = 10, reference medium at the arithmetic mean.
 
-A step is one iteration of the solver: one application of the fixed-point map
-with the RPM recombination, projections, Newton step and (every n_max + 1
-iterations) basis growth.  The timed region is one solve of exactly K steps
-from the uniform start; value = voxels x (steps + JVP map applications) / s.
+A step is one iteration of the solver at its steady state: one application of
+the fixed-point map with the RPM recombination, projections and Newton step on
+a basis of p_max columns.  An untimed solve builds the basis; the timed region
+is one solve of exactly K steps that carries it (no growth inside the window);
+value = voxels x (steps + JVP map applications) / s.  The growth events, the
+time to tolerance, the small configurations (32^2 disk, 64^3 spheres) and the
+CPU oracle legs are reported beside it.
 
 Prints one JSON line (see the keys below).  --gpus above 1 is refused: this
 build runs on one GPU.
@@ -30,15 +33,15 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_128cube_voids_fp32.json")
 KERNEL_SOURCES = ["include/rpmfft.h", "paper_2003_07720_amd/csrc/rpm_device.h",
                   "paper_2003_07720_amd/csrc/rpm_kernels.h", "paper_2003_07720_amd/csrc/rpm_solver.hip"]
-# kernel symbols (FP32 path) behind each timing class of rpm_stats
+# kernel symbols behind each timing class of rpm_stats ({T}: float or double)
 CLASS_SYMBOLS = {
-    "xfwd": r"rpm::k_xfwd<float, (true|false), false(, \d+)?(, (true|false))?>",
-    "yfwd": r"rpm::k_ypipe<float, -1, \d+(, (true|false))?>|rpm::k_yfwd<float>",
-    "gamma": r"rpm::k_(gamma|gpipe)<float, false(, (true|false))?>",
-    "yinv": r"rpm::k_ypipe<float, 1, \d+(, (true|false))?>|rpm::k_yinv<float>",
-    "xinv": r"rpm::k_xinv<float, false(, \d+)?(, (true|false))?>",
-    "project": r"rpm::k_gdots<float, float, [12], 0>",
-    "recombine": r"rpm::k_recombine<float>",
+    "xfwd": r"rpm::k_xfwd<{T}, (true|false), false(, \d+)?(, (true|false))?>",
+    "yfwd": r"rpm::k_ypipe<{T}, -1, \d+(, (true|false))?>|rpm::k_yfwd<{T}>",
+    "gamma": r"rpm::k_(gamma|gpipe)<{T}, false(, (true|false))?>",
+    "yinv": r"rpm::k_ypipe<{T}, 1, \d+(, (true|false))?>|rpm::k_yinv<{T}>",
+    "xinv": r"rpm::k_xinv<{T}, false(, \d+)?(, (true|false))?>",
+    "project": r"rpm::k_gdots<{T}, {T}, [12], 0>",
+    "recombine": r"rpm::k_recombine<{T}>",
 }
 
 
@@ -52,11 +55,12 @@ def source_digest():
     return h.hexdigest()
 
 
-def traffic_from(fetch_csv, write_csv, copy_mib, steps, seed, out_path):
-    """Per-launch HBM bytes of each kernel class from two rocprofv3 --pmc runs of
-    this script (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by
-    what the same counter reads for the plain copy of copy_mib MiB that
-    --calibrate-copy-mib appends to the run."""
+def traffic_from(fetch_csv, write_csv, copy_mib, steps, seed, out_path, precision, n, p):
+    """Per-launch HBM bytes of each kernel class in the steady-state window (the
+    last `steps` dispatches of the class: the timed solve, basis at p_max) from
+    two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+    dispatch), each scaled by what the same counter reads for the plain copy of
+    copy_mib MiB that --calibrate-copy-mib appends to the run."""
     import csv
     import re
 
@@ -65,12 +69,17 @@ def traffic_from(fetch_csv, write_csv, copy_mib, steps, seed, out_path):
         with open(path) as fh:
             for r in csv.DictReader(fh):
                 if r["Counter_Name"] == counter:
-                    rows.append((r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
-        return rows
+                    rows.append((int(r.get("Dispatch_Id", len(rows))), r["Kernel_Name"],
+                                 float(r["Counter_Value"]) * 1024.0))
+        rows.sort()
+        return [(k, v) for _, k, v in rows]
 
+    T = "float" if precision == "fp32" else "double"
     copy_bytes = copy_mib * float(1 << 20)
-    out = {"workload": "128^3 voids FP32 (bench.py defaults)", "steps": steps, "seed": seed, "copy_mib": copy_mib,
-           "source_sha256": source_digest(), "classes": {}}
+    out = {"workload": f"{n}^3 voids {precision} (bench.py defaults), steady state at p_max", "steps": steps,
+           "seed": seed, "precision": precision, "n": n, "p": p, "copy_mib": copy_mib,
+           "source_sha256": source_digest(),
+           "classes": {}}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = load(path, counter)
         # the calibration copies are the three largest copy dispatches
@@ -78,7 +87,8 @@ def traffic_from(fetch_csv, write_csv, copy_mib, steps, seed, out_path):
         scale = copy_bytes / (sum(copies) / len(copies))
         out[counter.lower() + "_scale"] = scale
         for cls, pat in CLASS_SYMBOLS.items():
-            vals = [v for k, v in rows if re.search(pat, k.split("(")[0])]
+            pat = pat.replace("{T}", T)
+            vals = [v for k, v in rows if re.search(pat, k.split("(")[0])][-steps:]
             if not vals:
                 continue
             c = out["classes"].setdefault(cls, {"dispatches": len(vals)})
@@ -91,15 +101,18 @@ def traffic_from(fetch_csv, write_csv, copy_mib, steps, seed, out_path):
     print(json.dumps(out, indent=1))
 
 
-def measured_traffic(cls, steps, seed):
-    """Counter-measured bytes per launch of a class, or None when absent or
-    measured on other sources or another step count."""
+def measured_traffic(cls, seed, precision, n, p):
+    """Counter-measured bytes per launch of a class in the steady state (basis at
+    p_max), or None when absent or measured on other sources, another cell or
+    another precision.  Steady-state launches of a class all move the same bytes,
+    so the figure does not depend on the number of steps."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != source_digest() or t.get("steps") != steps or t.get("seed") != seed:
+    if (t.get("source_sha256") != source_digest() or t.get("seed") != seed or t.get("precision") != precision
+            or t.get("n") != n or t.get("p") != p):
         return None
     c = t.get("classes", {}).get(cls)
     return None if c is None else c.get("traffic_bytes_per_launch")
@@ -119,7 +132,13 @@ def parse():
                     help="looser tolerances timed for RPM and the basic scheme (comma list, '' = none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
+    ap.add_argument("--no-small", action="store_true", help="skip the 32^2 disk and 64^3 sphere rows")
     ap.add_argument("--cpu-steps", type=int, default=14, help="oracle map applications in the CPU sample")
+    ap.add_argument("--cpu-c2-maps", type=int, default=4,
+                    help="single-threaded oracle map applications sampled on the 64^3 spheres")
+    ap.add_argument("--p-max", type=int, default=32, help="basis cap")
+    ap.add_argument("--basis-iters", type=int, default=400,
+                    help="steps of the untimed solve that builds the basis before the timed window")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="after the run, copy a float32 buffer of this many MiB three times (a plain copy kernel "
                          "of known size that scales hardware byte counters)")
@@ -131,8 +150,8 @@ def parse():
                          "(FP64 and FP32 refined), timed; prints its own JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of "
-                         "'bench.py --warmup 0 --no-cpu --no-ttt --calibrate-copy-mib M' into per-launch traffic "
-                         "(written to profiles/)")
+                         "'bench.py --warmup 0 --no-cpu --no-ttt --no-small --calibrate-copy-mib M' into "
+                         "per-launch traffic (written to profiles/)")
     return ap.parse_args()
 
 
@@ -224,11 +243,83 @@ def stress_bench():
                       "rows": rows}), flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_legs(a, w_c3, phases_c3, E0_c3, N_c3, gpu_iters_c2):
+    """The oracle on the host: the 128^3 headline cell on all threads (the
+    cpu_baseline of the JSON line), and single-threaded legs on the 32^2 disk
+    (basic and RPM to 1e-8, whole solves) and one load case of the 64^3
+    spheres (seconds per map application, times the GPU's iteration count)."""
+    import oracle as O
+    from paper_2003_07720_amd import microstructure as M
+
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    c0 = time.perf_counter()
+    rc = O.solve(w_c3["phase"], O.lame_table(phases_c3), O.lame(E0_c3, 0.3), w_c3["E"], scheme="rpm", tol=a.tol,
+                 max_iter=a.cpu_steps, n_max=10, p_max=32)
+    c1 = time.perf_counter()
+    base = dict(value=N_c3 * (rc["iterations"] + rc["jvps"]) / (c1 - c0), unit="voxel-iters/s", cores=cores,
+                kind="oracle", cpu=cpu_model(),
+                sample=f"{rc['iterations']} map applications and {rc['jvps']} JVPs of the FP64 oracle (literal "
+                       f"18-transform map, RPM) on the same {a.n}^3 void cell, {c1 - c0:.1f} s, OpenMP threads")
+    legs = {}
+    # single-threaded legs: a child process with OMP_NUM_THREADS=1 (the OpenMP
+    # runtime of this process is already sized)
+    import subprocess
+
+    code = r"""
+import json, sys, time
+import numpy as np
+sys.path.insert(0, %r)
+import oracle as O
+from paper_2003_07720_amd import microstructure as M
+out = {}
+w = M.workload_disk32()
+for scheme in ("basic", "rpm"):
+    t0 = time.perf_counter()
+    r = O.solve(w["phase"], O.lame_table(w["phases"]), O.lame(*w["ref"]), w["E"], scheme=scheme, tol=w["tol"],
+                max_iter=20000, n_max=10, p_max=32)
+    out["disk32_" + scheme] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"],
+                                  seconds=round(time.perf_counter() - t0, 4))
+s = M.workload_spheres64()
+k = %d
+t0 = time.perf_counter()
+r = O.solve(s["phase"], O.lame_table(s["phases"]), O.lame(*s["ref"]), np.array([0, 0, 0.01, 0, 0, 0.]),
+            scheme="rpm", tol=1e-6, max_iter=k, n_max=10, p_max=32)
+el = time.perf_counter() - t0
+out["spheres64_zz_sample"] = dict(map_applications=r["iterations"] + r["jvps"], seconds=round(el, 3),
+                                  s_per_map=el / (r["iterations"] + r["jvps"]))
+print(json.dumps(out))
+""" % (ROOT, a.cpu_c2_maps)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    pr = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if pr.returncode == 0:
+        legs = json.loads(pr.stdout.strip().splitlines()[-1])
+        sm = legs["spheres64_zz_sample"]
+        if gpu_iters_c2:
+            sm["gpu_map_applications"] = gpu_iters_c2
+            sm["estimated_solve_s"] = round(sm["s_per_map"] * gpu_iters_c2, 1)
+    else:
+        legs = {"error": pr.stderr[-2000:]}
+    legs["threads"] = 1
+    legs["cpu"] = cpu_model()
+    return base, legs
+
+
 def main():
     a = parse()
     if a.traffic_from:
         traffic_from(a.traffic_from[0], a.traffic_from[1], a.calibrate_copy_mib or 1024, a.steps, a.seed,
-                     TRAFFIC_FILE)
+                     TRAFFIC_FILE, a.precision, a.n, a.p_max)
         return
     if a.table1 and a.gpus == 1:
         table1()
@@ -254,150 +345,73 @@ def main():
     l0 = B.lame_from_young(E0, 0.3)
     phase = torch.from_numpy(w["phase"]).to("cuda")
     N = phase.numel()
-    common = dict(scheme="rpm", precision=a.precision, n_max=10, p_max=32, kappa=0.1, tol=a.tol, check_every=32)
-    ws = B.make_workspace(tuple(phase.shape), B.make_options(max_iter=max(a.steps, a.ttt_iters, a.warmup) + 1,
-                                                            **common))
+    prec_txt = "FP32 fields + FP64 RPM steps" if a.precision == "fp32" else "FP64 fields and RPM steps"
+    common = dict(scheme="rpm", precision=a.precision, n_max=10, p_max=a.p_max, kappa=0.1, tol=a.tol,
+                  check_every=32)
+    cap = max(a.steps, a.ttt_iters, a.warmup, a.basis_iters) + 1
+    ws = B.make_workspace(tuple(phase.shape), B.make_options(max_iter=cap, **common))
     print(f"bench: workload {a.n}^3 voids vf={w['info']['vf']:.4f} ({w['info']['n_spheres']} spheres), "
           f"{a.precision}, warmup {a.warmup}, steps {a.steps}", file=sys.stderr, flush=True)
 
-    # warm-up (untimed)
+    # 1. untimed: build the basis up to p_max (a plain solve from the uniform
+    # start; growth every n_max + 1 steps)
+    rb = B.fft_solve(phase, lt, l0, E, B.make_options(max_iter=a.basis_iters, **dict(common, refine=0)),
+                     workspace=ws, want_eps=False)
+    p_steady = rb["basis_dim"]
+    print(f"bench: basis solve {rb['iterations']} steps, {rb['jvps']} JVPs, p = {p_steady}", file=sys.stderr,
+          flush=True)
+    # steady-state windows: the basis carried (reuse_basis), no growth (p = p_max),
+    # a tolerance no step reaches so every step does its full work
+    steady = dict(common, reuse_basis=1, tol=1e-15, refine=0)
     if a.warmup > 0:
-        B.fft_solve(phase, lt, l0, E, B.make_options(max_iter=a.warmup, **common), workspace=ws, want_eps=False)
-    torch.cuda.synchronize()
-
-    # timed region: exactly K steps; HIP events on the solver's stream bracket
-    # only the two basis-stream classes (one of them dominates), so the other
-    # kernels run back to back as they do without profiling
-    dom_classes = ("project", "recombine")
-    mask = sum(1 << B.KERNEL_NAMES.index(k) for k in dom_classes)
-    opts = B.make_options(max_iter=a.steps, profile=1, profile_classes=mask, **common)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = B.fft_solve(phase, lt, l0, E, opts, workspace=ws, want_eps=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    el = t1 - t0
-    steps = r["iterations"]
-    fcalls = steps + r["jvps"]
-    value = N * fcalls / el
-    print(f"bench: {steps} steps, {r['jvps']} JVPs, p={r['basis_dim']}, residual {r['residual']:.3e}, "
-          f"{el * 1e3:.1f} ms", file=sys.stderr, flush=True)
-
-    # roofline of the dominant kernel class (events of the timed region)
-    kms = r["kernel_ms"]
-    dom = max((k for k in dom_classes if r["kernel_launches"][k] > 0), key=lambda k: kms[k])
-    launches = r["kernel_launches"][dom]
-    avg_ms = kms[dom] / launches
-    bytes_per_launch = r["kernel_bytes"][dom] / launches
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom, a.steps, a.seed) if a.precision == "fp32" and a.n == 128 else None
-
-    # every kernel class, from a second (untimed) run of the same K steps with
-    # events around every class
-    rk = B.fft_solve(phase, lt, l0, E, B.make_options(max_iter=a.steps, profile=1, **common), workspace=ws,
+        B.fft_solve(phase, lt, l0, E, B.make_options(max_iter=a.warmup, **steady), workspace=ws, want_eps=False)
+    # 2. untimed: the same K steps with HIP events around every kernel class
+    rk = B.fft_solve(phase, lt, l0, E, B.make_options(max_iter=a.steps, profile=1, **steady), workspace=ws,
                      want_eps=False)
     kall = rk["kernel_ms"]
     per_kernel = {k: dict(ms_total=round(kall[k], 4), launches=rk["kernel_launches"][k],
                           avg_us=round(1e3 * kall[k] / max(rk["kernel_launches"][k], 1), 3),
                           gbs=round(rk["kernel_bytes"][k] / max(kall[k], 1e-12) / 1e6, 1))
                   for k in kall if rk["kernel_launches"][k] > 0}
-    print(f"bench: all-class profile run {1e3 * rk['seconds']:.1f} ms", file=sys.stderr, flush=True)
+    # the dominant class: the largest total event time among the classes with
+    # algorithmic bytes (the small reduction / finalize kernels have none)
+    dom = max((k for k in kall if rk["kernel_launches"][k] > 0 and rk["kernel_bytes"][k] > 0), key=lambda k: kall[k])
+    # 3. timed region: K steps, events only around the dominant class
+    mask = 1 << B.KERNEL_NAMES.index(dom)
+    opts = B.make_options(max_iter=a.steps, profile=1, profile_classes=mask, **steady)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = B.fft_solve(phase, lt, l0, E, opts, workspace=ws, want_eps=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    steps = r["iterations"]
+    fcalls = steps + r["jvps"]
+    value = N * fcalls / el
+    print(f"bench: timed {steps} steps at p = {r['basis_dim']}, {r['jvps']} JVPs, {el * 1e3:.1f} ms, "
+          f"dominant class {dom}", file=sys.stderr, flush=True)
+    launches = r["kernel_launches"][dom]
+    avg_ms = r["kernel_ms"][dom] / launches
+    bytes_per_launch = r["kernel_bytes"][dom] / launches
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, a.seed, a.precision, a.n, r["basis_dim"])
 
-    # time to tolerance (plain RPM, uniform start)
+    # time to tolerance: plain RPM from the uniform start and an empty basis
     ttt = None
     ttt_info = {}
     if not a.no_ttt:
-        o2 = B.make_options(max_iter=a.ttt_iters, **common)
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        r2 = B.fft_solve(phase, lt, l0, E, o2, workspace=ws, want_eps=False, history_cap=a.ttt_iters + 1)
-        torch.cuda.synchronize()
-        s1 = time.perf_counter()
-        ttt_info = dict(status=r2["status"], iterations=r2["iterations"], jvps=r2["jvps"], p=r2["basis_dim"],
-                        residual=r2["residual"], seconds=round(s1 - s0, 4))
-        if r2["status"] == "RPM_OK":
-            ttt = s1 - s0
-        print(f"bench: time-to-tol solve {ttt_info}", file=sys.stderr, flush=True)
-        # looser tolerances: plain RPM against the basic scheme (Algorithm 1), each timed
-        loose = {}
-        for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
-            for scheme in ("rpm", "basic"):
-                o3 = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, scheme=scheme, refine=0))
-                torch.cuda.synchronize()
-                u0 = time.perf_counter()
-                r3 = B.fft_solve(phase, lt, l0, E, o3, workspace=ws, want_eps=False)
-                torch.cuda.synchronize()
-                u1 = time.perf_counter()
-                loose[f"{scheme}@{tl:g}"] = dict(status=r3["status"], iterations=r3["iterations"],
-                                                 seconds=round(u1 - u0, 4), residual=r3["residual"])
-        ttt_info["looser_tolerances"] = loose
-        print(f"bench: looser tolerances {loose}", file=sys.stderr, flush=True)
-        # warm start (eps0) from the same cell on the half-resolution grid (the
-        # phase of every second voxel), solved to the same tolerance, its strain
-        # repeated over 2 x 2 x 2 voxels; the time includes the coarse solve
-        warm = {}
-        ph_c = phase[::2, ::2, ::2].contiguous()
-        o_c = B.make_options(max_iter=a.ttt_iters, **dict(common, refine=0))
-        ws_c = B.make_workspace(tuple(ph_c.shape), o_c)
-        for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
-            o4 = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, refine=0))
-            torch.cuda.synchronize()
-            v0 = time.perf_counter()
-            rc = B.fft_solve(ph_c, lt, l0, E, o4, workspace=ws_c)
-            e0 = rc["eps"]
-            for d in (1, 2, 3):
-                e0 = e0.repeat_interleave(2, dim=d)
-            rf = B.fft_solve(phase, lt, l0, E, o4, eps0=e0.contiguous(), workspace=ws, want_eps=False)
-            torch.cuda.synchronize()
-            v1 = time.perf_counter()
-            warm[f"rpm@{tl:g}"] = dict(status=rf["status"], iterations=rf["iterations"],
-                                       coarse_iterations=rc["iterations"], seconds=round(v1 - v0, 4),
-                                       residual=rf["residual"])
-        ttt_info["coarse_grid_warm_start"] = warm
-        print(f"bench: coarse-grid warm start {warm}", file=sys.stderr, flush=True)
-        # basis warm start: the unstable basis (Z, W, H) built by the solve of
-        # another load case on the same cell (uniaxial xx) seeds the zz solve.
-        # Exact, since the linear part of the map does not depend on the mean
-        # strain; the basis solve is timed separately (amortised over the load
-        # cases of an effective tensor)
-        bw = {}
-        Exx = np.zeros(6)
-        Exx[0] = E[2]
-        for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
-            ob = B.make_options(max_iter=min(a.ttt_iters, 400), **dict(common, tol=tl, refine=0))
-            torch.cuda.synchronize()
-            b0 = time.perf_counter()
-            rb = B.fft_solve(phase, lt, l0, Exx, ob, workspace=ws, want_eps=False)
-            torch.cuda.synchronize()
-            b1 = time.perf_counter()
-            ow = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, refine=0, reuse_basis=1))
-            rw = B.fft_solve(phase, lt, l0, E, ow, workspace=ws, want_eps=False)
-            torch.cuda.synchronize()
-            b2 = time.perf_counter()
-            bw[f"rpm@{tl:g}"] = dict(status=rw["status"], iterations=rw["iterations"], p=rw["basis_dim"],
-                                     seconds=round(b2 - b1, 4), residual=rw["residual"],
-                                     basis_solve=dict(status=rb["status"], iterations=rb["iterations"],
-                                                      p=rb["basis_dim"], seconds=round(b1 - b0, 4)))
-        ttt_info["basis_warm_start"] = bw
-        print(f"bench: basis warm start {bw}", file=sys.stderr, flush=True)
+        ttt, ttt_info = time_to_tol(a, B, M, torch, phase, lt, l0, E, common, ws)
 
-    # CPU oracle on a bounded sample of the same workload
+    # the small configurations on the GPU: the 32^2 disk (basic and RPM to 1e-8, FP64)
+    small = {} if a.no_small else disk32_row(B, M, torch)
+
     cpu = None
+    cpu_single = None
     if not a.no_cpu:
-        import oracle as O
-
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        c0 = time.perf_counter()
-        rc = O.solve(w["phase"], O.lame_table(phases), O.lame(E0, 0.3), E, scheme="rpm", tol=a.tol,
-                     max_iter=a.cpu_steps, n_max=10, p_max=32)
-        c1 = time.perf_counter()
-        cpu = dict(value=N * (rc["iterations"] + rc["jvps"]) / (c1 - c0), unit="voxel-iters/s", cores=cores,
-                   kind="oracle",
-                   sample=f"{rc['iterations']} map applications of the FP64 oracle (literal 18-transform map, "
-                          f"RPM) on the same {a.n}^3 void cell, {c1 - c0:.1f} s")
+        c2 = small.get("spheres64_zz_fp64", {}).get("map_applications")
+        cpu, cpu_single = cpu_legs(a, w, phases, E0, N, c2)
 
     out = {
-        "metric": "voxel-iters/s + time to 1e-6 residual at 128\u00b3 voids; warm-start vs plain RPM",
+        "metric": "voxel-iters/s + time to 1e-6 residual at 128³ voids; warm-start vs plain RPM",
         "value": value,
         "unit": "voxel-iters/s",
         "n_gpus": 1,
@@ -411,14 +425,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.n}^3 spherical voids (radii {6 * a.n / 128:g}-{12 * a.n / 128:g} voxels, "
                                f"vf {w['info']['vf']:.3f}, seed {a.seed}), void stiffness 1e-8, eps_zz 0.01, "
-                               f"plain RPM (no warm start), p_max 32, n_max 10, FP32 fields + FP64 RPM steps",
-                   "voxels": N, "p_end": r["basis_dim"], "jvps": r["jvps"],
-                   "time_to_tol_s": ttt, "time_to_tol_run": ttt_info},
+                               f"E0 = {E0:.6g} (arithmetic mean), plain RPM (no warm start), p_max {a.p_max}, "
+                               f"n_max 10, {prec_txt}; timed: {steps} steady-state steps at p = "
+                               f"{r['basis_dim']} (basis carried from an untimed solve)",
+                   "voxels": N, "p_timed": r["basis_dim"], "jvps_timed": r["jvps"],
+                   "time_to_tol_s": ttt, "time_to_tol_run": ttt_info, "small_configs": small},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "avg_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per_launch},
         "kernels": per_kernel,
         "cpu_baseline": cpu,
+        "cpu_single_thread": cpu_single,
     }
     print(json.dumps(out), flush=True)
     if a.calibrate_copy_mib > 0:
@@ -427,6 +444,100 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
+
+
+def time_to_tol(a, B, M, torch, phase, lt, l0, E, common, ws):
+    """Plain RPM from the uniform start to tol (capped), then looser tolerances
+    for RPM and the basic scheme, and the two warm starts."""
+    o2 = B.make_options(max_iter=a.ttt_iters, **common)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    r2 = B.fft_solve(phase, lt, l0, E, o2, workspace=ws, want_eps=False, history_cap=a.ttt_iters + 1)
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    h = r2["history"]
+    info = dict(status=r2["status"], iterations=r2["iterations"], jvps=r2["jvps"], p=r2["basis_dim"],
+                residual=r2["residual"], residual_fp64=r2["residual_fp64"], refinements=r2["refinements"],
+                seconds=round(s1 - s0, 4),
+                error_at={str(k): float(h[k]) for k in (100, 300, 1000, 2000, 4000) if k < len(h)})
+    ttt = (s1 - s0) if r2["status"] == "RPM_OK" else None
+    print(f"bench: time-to-tol solve {info}", file=sys.stderr, flush=True)
+    loose = {}
+    for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
+        for scheme in ("rpm", "basic"):
+            o3 = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, scheme=scheme, refine=0))
+            torch.cuda.synchronize()
+            u0 = time.perf_counter()
+            r3 = B.fft_solve(phase, lt, l0, E, o3, workspace=ws, want_eps=False)
+            torch.cuda.synchronize()
+            u1 = time.perf_counter()
+            loose[f"{scheme}@{tl:g}"] = dict(status=r3["status"], iterations=r3["iterations"],
+                                             seconds=round(u1 - u0, 4), residual=r3["residual"])
+    info["looser_tolerances"] = loose
+    print(f"bench: looser tolerances {loose}", file=sys.stderr, flush=True)
+    # basis warm start: the basis another load case (uniaxial xx) built on the
+    # same cell, capped at half of p_max so the solve keeps room to grow
+    bw = {}
+    Exx = np.zeros(6)
+    Exx[0] = E[2]
+    for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
+        ob = B.make_options(max_iter=min(a.ttt_iters, 10 * (a.p_max // 2) + 12),
+                            **dict(common, tol=tl, refine=0, p_max=a.p_max))
+        torch.cuda.synchronize()
+        b0 = time.perf_counter()
+        rb = B.fft_solve(phase, lt, l0, Exx, ob, workspace=ws, want_eps=False)
+        torch.cuda.synchronize()
+        b1 = time.perf_counter()
+        ow = B.make_options(max_iter=a.ttt_iters, **dict(common, tol=tl, refine=0, reuse_basis=1))
+        rw = B.fft_solve(phase, lt, l0, E, ow, workspace=ws, want_eps=False)
+        torch.cuda.synchronize()
+        b2 = time.perf_counter()
+        bw[f"rpm@{tl:g}"] = dict(status=rw["status"], iterations=rw["iterations"], p_start=rb["basis_dim"],
+                                 p_end=rw["basis_dim"], seconds=round(b2 - b1, 4), residual=rw["residual"],
+                                 basis_solve=dict(status=rb["status"], iterations=rb["iterations"],
+                                                  seconds=round(b1 - b0, 4)))
+    info["basis_warm_start"] = bw
+    print(f"bench: basis warm start {bw}", file=sys.stderr, flush=True)
+    return ttt, info
+
+
+def disk32_row(B, M, torch):
+    """The 32^2 disk (basic and RPM to 1e-8, FP64) and one load case of the 64^3
+    spheres (E0 at the stiff modulus, RPM to 1e-6, FP64 and FP32 refined) on the
+    GPU, timed after an untimed run of the same call."""
+    out = {}
+    w = M.workload_disk32()
+    ph = torch.from_numpy(w["phase"]).to("cuda")
+    lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
+    l0 = B.lame_from_young(*w["ref"])
+    for scheme in ("basic", "rpm"):
+        o = B.make_options(scheme=scheme, tol=w["tol"], max_iter=20000, precision="fp64", check_every=32)
+        B.fft_solve(ph, lt, l0, w["E"], o, want_eps=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = B.fft_solve(ph, lt, l0, w["E"], o, want_eps=False)
+        torch.cuda.synchronize()
+        out["disk32_" + scheme] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"],
+                                       seconds=round(time.perf_counter() - t0, 5))
+    s = M.workload_spheres64()
+    ph = torch.from_numpy(s["phase"]).to("cuda")
+    lt = np.array([B.lame_from_young(*p) for p in s["phases"]])
+    l0 = B.lame_from_young(*s["ref"])
+    Ezz = np.array([0, 0, 0.01, 0, 0, 0.0])
+    for prec in ("fp64", "fp32"):
+        o = B.make_options(scheme="rpm", tol=1e-6, max_iter=20000, precision=prec, check_every=32)
+        ws = B.make_workspace(tuple(ph.shape), o)
+        B.fft_solve(ph, lt, l0, Ezz, o, workspace=ws, want_eps=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = B.fft_solve(ph, lt, l0, Ezz, o, workspace=ws, want_eps=False)
+        torch.cuda.synchronize()
+        out[f"spheres64_zz_{prec}"] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"],
+                                           map_applications=r["iterations"] + r["jvps"],
+                                           refinements=r["refinements"], residual_fp64=r["residual_fp64"],
+                                           seconds=round(time.perf_counter() - t0, 4))
+    print(f"bench: small configurations {out}", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":

@@ -81,9 +81,11 @@ enum { RPM_MAP_LS = 0,             /* the Lippmann-Schwinger map F (Algorithm 1)
                                        taken as -beta C0:eps                      */
 
 enum { RPM_FP64 = 0,         /* fields, FFTs and Z in double                     */
-       RPM_FP32 = 1 };       /* fields, FFTs and Z in float; reductions, norms,
-                                Gram-Schmidt coefficients, H and the Newton
-                                solve in double                                   */
+       RPM_FP32 = 1 };       /* fields, FFTs, Z and W in float; reductions,
+                                norms, Gram-Schmidt, the compatible projection
+                                of new basis columns, the Jacobian-vector
+                                products that form H, H and the Newton solve in
+                                double                                            */
 
 /* kernel classes of rpm_stats.kernel_* (profile = 1) */
 enum { RPM_K_XFWD = 0, RPM_K_YFWD, RPM_K_GAMMA, RPM_K_YINV, RPM_K_XINV, RPM_K_REDUCE, RPM_K_FINAL,
@@ -140,6 +142,12 @@ typedef struct {
                                  k for class k (< 1 << RPM_NKERNEL); 0 = every
                                  class.  Fewer classes, fewer event records
                                  between the kernels of the timed solve.         */
+    int32_t stall_window;     /* RPM_FP32 with refine > 0: the FP32 stage (and
+                                 each correction solve) also stops when its
+                                 error has not fallen below 0.9 x its lowest
+                                 value for this many iterations (FP32 rounding
+                                 floor); refinement then continues from that
+                                 field.  0 = never (>= 0)                        */
 } rpm_options;
 
 typedef struct {
@@ -167,7 +175,7 @@ typedef struct {
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
  * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
  * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2,
- * no profiling (profile_classes 0). */
+ * no profiling (profile_classes 0), stall_window 400. */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and
@@ -285,6 +293,14 @@ rpm_status rpm_fft_apply_static(const rpm_problem *pr, const double E[6], const 
 
 /* Current basis dimension stored in a workspace (0 if never used).  HOST p. */
 rpm_status rpm_workspace_basis_dim(const void *workspace, size_t ws_bytes, int32_t *p, void *hip_stream);
+
+/* The reduced matrix H = Z^T F_u Z of the basis a workspace holds (Sec. 3:
+ * the Jacobian of the map restricted to the unstable subspace, bordered by one
+ * row and column per added column): HOST H receives p x p doubles, row major
+ * with leading dimension ld (>= p; at most ld x ld are written), HOST p the
+ * basis dimension (0 if the workspace was never used). */
+rpm_status rpm_workspace_h(const void *workspace, size_t ws_bytes, double *H, int32_t ld, int32_t *p,
+                           void *hip_stream);
 
 /* Static string naming a status code. */
 const char *rpm_status_string(rpm_status s);

@@ -43,7 +43,7 @@ class RpmOptions(ctypes.Structure):
                 ("replay", ctypes.POINTER(ctypes.c_int32)), ("replay_len", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("profile_classes", ctypes.c_int32)]
+                ("profile_classes", ctypes.c_int32), ("stall_window", ctypes.c_int32)]
 
 
 class RpmStats(ctypes.Structure):
@@ -74,16 +74,17 @@ _lib.rpm_fft_solve_stress.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, 
                                       ctypes.c_size_t, _vp]
 _lib.rpm_fft_seed_basis.argtypes = [_P(RpmProblem), _P(RpmOptions), _vp, ctypes.c_int32, _P(ctypes.c_int32), _vp,
                                     ctypes.c_size_t, _vp]
+_lib.rpm_workspace_h.argtypes = [_vp, ctypes.c_size_t, _dp, ctypes.c_int32, _P(ctypes.c_int32), _vp]
 _lib.rpm_status_string.argtypes = [ctypes.c_int]
 _lib.rpm_status_string.restype = ctypes.c_char_p
 for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_apply_static", "rpm_fft_solve", "rpm_fft_effective_tensor",
-           "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress"):
+           "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress", "rpm_workspace_h"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply",
             "rpm_fft_apply_static", "rpm_fft_solve",
             "rpm_fft_effective_tensor", "rpm_fft_solve_stress", "rpm_fft_seed_basis", "rpm_workspace_basis_dim",
-            "rpm_status_string"]
+            "rpm_workspace_h", "rpm_status_string"]
 
 
 class RpmError(RuntimeError):
@@ -347,3 +348,14 @@ def basis_dim(workspace):
     if rc != 0:
         raise RpmError(rc, "rpm_workspace_basis_dim")
     return p.value
+
+
+def workspace_h(workspace):
+    """H = Z^T F_u Z of the basis a workspace holds (p x p numpy array)."""
+    H = np.zeros((64, 64))
+    p = ctypes.c_int32()
+    rc = _lib.rpm_workspace_h(ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), H.ctypes.data_as(_dp), 64,
+                              ctypes.byref(p), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_workspace_h")
+    return H[:p.value, :p.value].copy()

@@ -72,7 +72,7 @@ struct DevState {
     int magic;         // kStateMagic once the workspace has been initialised
     int cfg[6];        // nx, ny, nz, precision, p_max, map the basis was built for
     int done;          // 1 once the iteration stopped (any reason)
-    int status;        // 0 converged, 1 not converged, 2 diverged, 3 singular
+    int status;        // 0 converged, 1 not converged, 2 diverged, 3 singular, 4 stalled
     int iters;         // main-loop F applications so far
     int p;             // basis dimension
     int singular;      // LU of I - H hit a tiny pivot
@@ -86,6 +86,9 @@ struct DevState {
     double E[6];       // prescribed mean strain of the current solve
     double Ezero[6];   // zeros (mean strain of Jacobian-vector products)
     double gnorm;      // norm of the shift field of a correction solve
+    double best_err;   // lowest error below 0.9 x the previous lowest (stall test)
+    int best_it;       // iteration at which best_err was reached
+    int stall_window;  // stop (status 4) after this many iterations without a new best_err; 0 = off
     double medium[6];  // lambda0, mu0, alpha, beta and a hash of the phase table the basis was built for
     double z[kMaxP], zeta[kMaxP], d[kMaxP];
     double zeta_ring[4][kMaxP];
@@ -1347,6 +1350,15 @@ __global__ __launch_bounds__(kThreads) void k_step_end(DevState* __restrict__ st
             } else if (it >= st->max_iter) {
                 st->status = 1;
                 st->done = 1;
+            } else if (st->stall_window > 0) {
+                // stalled: no error below 0.9 x the lowest one for stall_window iterations
+                if (err < 0.9 * st->best_err) {
+                    st->best_err = err;
+                    st->best_it = it;
+                } else if (it - st->best_it >= st->stall_window) {
+                    st->status = 4;
+                    st->done = 1;
+                }
             }
         }
         snow = st->done;
@@ -1716,10 +1728,10 @@ __global__ __launch_bounds__(kThreads) void k_residual_shift(const double* __res
 }
 
 template <typename TD>
-__global__ void k_add_correction(double* __restrict__ eps, const TD* __restrict__ d, long long n)
+__global__ void k_add_correction(double* __restrict__ eps, const TD* __restrict__ d, double s, long long n)
 {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) eps[i] += (double)d[i];
+    if (i < n) eps[i] += s * (double)d[i];
 }
 
 template <typename T>

@@ -373,6 +373,10 @@ struct Ctx {
     double alpha = 2.0, beta = 2.0;
     Prof prof;
     bool hip_error = false;
+    // FP32 fields: the FP64 pipeline in the same workspace, which evaluates
+    // the Jacobian-vector products of H and the compatible projection of new
+    // basis columns (null for FP64 fields)
+    Ctx<double>* sub = nullptr;
 
     template <typename P>
     P* at(size_t off) { return reinterpret_cast<P*>(ws + off); }
@@ -605,7 +609,7 @@ void reduce_cols(Ctx<T>& c, const double* part, int G, long long bs, long long c
 // Initialise or re-validate the workspace header; uploads the tables.
 template <typename T>
 rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool want_reuse, int* p_io,
-                   double tol, double gnorm = 1.0)
+                   double tol, double gnorm = 1.0, int stall = 0)
 {
     const Geo& g = c.sh.g;
     DevState hs;
@@ -644,6 +648,9 @@ rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool 
     hs.gnorm = gnorm;
     hs.err0 = 0.0;
     hs.err = 0.0;
+    hs.best_err = 1e300;
+    hs.best_it = 0;
+    hs.stall_window = stall;
     for (int i = 0; i < 6; ++i) hs.Ezero[i] = 0.0;
     *p_io = hs.p;
     // twiddles exp(-2 pi i e / n) computed in long double on the host; the
@@ -744,15 +751,36 @@ int add_columns(Ctx<T>& c, int& p, double* const* v, int* jvps)
     k_col_put2<T><<<gb, 256, 0, c.s>>>(v[0], v1, keep0 ? 1.0 / vn0 : 0.0, c01, keep1 ? 1.0 / vn1 : 0.0,
                                        (keep0 ? 1 : 0) | (keep1 ? 2 : 0), c.Zb(), p, c.pmax, tmp,
                                        keep0 ? tmp2 : tmp, nel);
-    // Jacobian-vector products w = F(z; E = 0)
+    // Jacobian-vector products w = F(z; E = 0) of the stored columns; with FP32
+    // fields they run in the FP64 pipeline on the exact FP64 values of the
+    // stored columns, and the H columns are formed from the FP64 products (W
+    // itself is stored rounded)
+    double* z64[2] = {nullptr, nullptr};
+    double* w64[2] = {nullptr, nullptr};
     for (int a = 0; a < nacc; ++a) {
-        run_F<T>(c, zc[a], 0, nullptr, zc[a], wout[a], OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
-        k_col_put<T, T><<<gb, 256, 0, c.s>>>(wout[a], 1.0, c.Wb(), p + a, c.pmax, nullptr, nel);
+        if (c.sub) {
+            Ctx<double>& sd = *c.sub;
+            z64[a] = sd.ring(a);
+            w64[a] = reinterpret_cast<double*>(wout[a]);
+            k_convert<T, double><<<gb, 256, 0, c.s>>>(zc[a], z64[a], 1.0, nel);
+            run_F<double>(sd, z64[a], 0, nullptr, z64[a], w64[a], OUT_XI, 0, DC_MEAN, sd.st->Ezero, nullptr);
+            k_col_put<double, T><<<gb, 256, 0, c.s>>>(w64[a], 1.0, c.Wb(), p + a, c.pmax, nullptr, nel);
+        } else {
+            run_F<T>(c, zc[a], 0, nullptr, zc[a], wout[a], OUT_XI, 0, DC_MEAN, c.st->Ezero, nullptr);
+            k_col_put<T, T><<<gb, 256, 0, c.s>>>(wout[a], 1.0, c.Wb(), p + a, c.pmax, nullptr, nel);
+        }
         ++*jvps;
     }
     // H columns <z_i, w_a> and Gram columns <z_i, z_a>, i <= p + a, in one pass
     const int ld = kMaxP + 2;
-    if (nacc == 1)
+    if (c.sub) {
+        if (nacc == 1)
+            launch_gdots<double, T, 2, 1>(c.s, Gq, Fields<double>{{w64[0], z64[0]}}, c.Zb(), p + 1, c.pmax, N,
+                                          c.pg(), kMaxP);
+        else
+            launch_gdots<double, T, 4, 1>(c.s, Gq, Fields<double>{{w64[0], z64[0], w64[1], z64[1]}}, c.Zb(), p + 2,
+                                          c.pmax, N, c.pg(), kMaxP);
+    } else if (nacc == 1)
         launch_gdots<T, T, 2, 1>(c.s, Gq, Fields<T>{{wout[0], zc[0]}}, c.Zb(), p + 1, c.pmax, N, c.pg(), kMaxP);
     else
         launch_gdots<T, T, 4, 1>(c.s, Gq, Fields<T>{{wout[0], zc[0], wout[1], zc[1]}}, c.Zb(), p + 2, c.pmax, N,
@@ -820,6 +848,15 @@ int grow_basis(Ctx<T>& c, int it, int nq, int& p, const rpm_options* o, int grow
     for (int col = 1; col >= 0; --col) {
         if (!use[col]) continue;
         double* v = col == 0 ? D1 : D0;
+        if (c.sub && !c.pol) {
+            // FP32 fields: projected by the FP64 pipeline, never rounded to FP32
+            Ctx<double>& sd = *c.sub;
+            double* a = sd.ring(3);
+            if (col == 0) k_convert<double, double><<<gb, 256, 0, c.s>>>(D1, a, 1.0 / T11, nel);
+            else k_convert_sub<double><<<gb, 256, 0, c.s>>>(D0, D1, r01, 1.0 / T22, a, nel);
+            project_compatible<double>(sd, a, v);
+            continue;
+        }
         if (col == 0) k_convert<double, T><<<gb, 256, 0, c.s>>>(D1, tmp, 1.0 / T11, nel);
         else k_convert_sub<T><<<gb, 256, 0, c.s>>>(D0, D1, r01, 1.0 / T22, tmp, nel);
         if (c.pol) {
@@ -886,6 +923,7 @@ struct Spec {
     double tol;
     double gnorm;
     bool reuse;
+    int stall;            // stall window of the error (0 = off)
 };
 
 template <typename T>
@@ -903,7 +941,7 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
     const Geo& g = c.sh.g;
     const long long N = g.N;
     int p = 0;
-    rpm_status rs = prepare(c, pr, o, sp.reuse, &p, sp.tol, sp.gnorm);
+    rpm_status rs = prepare(c, pr, o, sp.reuse, &p, sp.tol, sp.gnorm, sp.stall);
     if (rs != RPM_OK) return rs;
     set_E(c, sp.E);
     const bool rpm = o->scheme == RPM_SCHEME_RPM && c.pmax > 0;
@@ -933,21 +971,25 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
             if (flags[0] || flags[2] >= o->max_iter) break;
             if (at_growth) {
                 int want = 0;
+                const int p_before = p;
                 const int added = grow_basis(c, it, nq, p, o, (int)so.decisions.size(), &want, &jvps);
                 if (added < 0) return RPM_E_HIP;
                 so.decisions.push_back(want);
                 ++growth;
                 nu = 0;
                 nq = 0;
+                // the current iterate: eps, or xi_prev while the basis was empty
+                const T* cur = (p_before > 0 || it == 1) ? c.eps() : c.ring(it - 1);
                 // projections of the current pair (eps, xi) on the grown basis, Newton step
-                project(c, c.ring(it), c.eps(), p, true);
+                project(c, c.ring(it), cur, p, true);
                 reduce_and_finalize(c, p, it, 1, true, done, sp.err_mode);
             }
         }
-        // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step
+        // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step (while
+        // the basis is empty eps = xi_prev, read where it lies)
         ++it;
         const T* xprev = c.ring(it - 1);
-        if (rpm) {
+        if (rpm && p > 0) {
             run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
             project(c, c.ring(it), c.eps(), p, false);
         } else {
@@ -959,7 +1001,9 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
     }
     if (!sync_read(c, &so.hs, c.st, sizeof(DevState))) return RPM_E_HIP;
     const int itf = std::max(so.hs.iters, 1);
-    so.final_it = (itf == 1 || rpm) ? c.eps() : c.ring(itf - 1);
+    // the input of the last map application: eps while a basis recombined it,
+    // the previous xi otherwise (the basis only grows between executed steps)
+    so.final_it = (itf == 1 || (rpm && p > 0)) ? c.eps() : c.ring(itf - 1);
     so.jvps += jvps;
     so.growth += growth;
     so.p = p;
@@ -1016,9 +1060,27 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
     // max(tol, kFp32Stage) and FP64 refinement takes the field to tol.
     const bool refine = sizeof(T) == 4 && o->refine > 0;
     const double stage_tol = refine ? std::max(o->tol, kFp32Stage) : o->tol;
-    Spec<T> sp{E, eps0, false, nullptr, 0, stage_tol, 1.0, reuse};
+    // with refinement, a stalled FP32 stage hands its field over to it
+    const int stall = refine ? o->stall_window : 0;
+    // FP32 fields: the FP64 pipeline (JVPs and projections of basis growth,
+    // certification, refinement)
+    Ctx<double> c64;
+    struct SubReset {
+        Ctx<T>& c;
+        ~SubReset() { c.sub = nullptr; }
+    } sub_reset{c};
+    rpm_status rs = RPM_OK;
+    if constexpr (sizeof(T) == 4) {
+        sub64_init(c64, c, o);
+        int p64 = 0;
+        rs = prepare(c64, pr, o, false, &p64, o->tol);
+        if (rs != RPM_OK) return rs;
+        set_E(c64, E);
+        c.sub = &c64;
+    }
+    Spec<T> sp{E, eps0, false, nullptr, 0, stage_tol, 1.0, reuse, stall};
     SolveOut<T> so;
-    rpm_status rs = run_solve(c, pr, o, sp, so);
+    rs = run_solve(c, pr, o, sp, so);
     if (rs < 0) return rs;
     const DevState hs_main = so.hs;
     if (st && st->history && st->history_cap > 0) {  // before correction solves reuse the buffer
@@ -1036,12 +1098,6 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
     const T* efin = so.final_it;
     bool rounded = false;  // outputs come from the FP64 field rounded to T
     if constexpr (sizeof(T) == 4) {
-        Ctx<double> c64;
-        sub64_init(c64, c, o);
-        int p64 = 0;
-        rs = prepare(c64, pr, o, false, &p64, o->tol);
-        if (rs != RPM_OK) return rs;
-        set_E(c64, E);
         k_convert<T, double><<<gb, 256, 0, c.s>>>(efin, c64.eps(), 1.0, nel);
         DevState h64;
         if ((rs = eval64(c64, h64)) != RPM_OK) return rs;
@@ -1049,7 +1105,7 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
         for (int i = 0; i < 6; ++i) sav[i] = h64.sig_hat0[i] / (double)N;
         const double zeros[6] = {0, 0, 0, 0, 0, 0};
         T* g32 = c.template at<T>(c.L.shift);
-        while (rs == RPM_OK && so.hs.status == 0 && res64 > o->tol && nref < o->refine) {
+        while (rs == RPM_OK && (so.hs.status == 0 || so.hs.status == 4) && res64 > o->tol && nref < o->refine) {
             // g = F64(eps64) - eps64, |g| in FP64
             k_residual_shift<T><<<c.sh.Gp, kThreads, 0, c.s>>>(c64.ring(1), c64.eps(), g32, N, c.pg());
             reduce_cols(c, c.pg(), c.sh.Gp, 1, 1, 1, c.gsum());
@@ -1057,7 +1113,7 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
             if (!sync_read(c, &g2, c.gsum(), sizeof(g2))) return RPM_E_HIP;
             const double gnorm = std::sqrt(std::max(g2, 0.0));
             if (!(gnorm > 0.0)) break;
-            Spec<T> sc{zeros, nullptr, true, g32, 1, o->refine_tol, gnorm, true};
+            Spec<T> sc{zeros, nullptr, true, g32, 1, o->refine_tol, gnorm, true, stall};
             SolveOut<T> si;
             rpm_status ri = run_solve(c, pr, o, sc, si);
             if (ri < 0) return ri;
@@ -1065,12 +1121,23 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
             so.growth += si.growth;
             so.p = si.p;
             so.decisions.insert(so.decisions.end(), si.decisions.begin(), si.decisions.end());
-            k_add_correction<T><<<gb, 256, 0, c.s>>>(c64.eps(), si.final_it, nel);
+            // a diverged or singular correction solve is not applied
+            if (si.hs.status == 2 || si.hs.status == 3) break;
+            k_add_correction<T><<<gb, 256, 0, c.s>>>(c64.eps(), si.final_it, 1.0, nel);
             if ((rs = eval64(c64, h64)) != RPM_OK) return rs;
+            ++nref;
+            if (!(h64.err < res64)) {
+                // the sweep did not lower the FP64 error: undo it and stop
+                k_add_correction<T><<<gb, 256, 0, c.s>>>(c64.eps(), si.final_it, -1.0, nel);
+                if ((rs = eval64(c64, h64)) != RPM_OK) return rs;
+                res64 = h64.err;
+                for (int i = 0; i < 6; ++i) sav[i] = h64.sig_hat0[i] / (double)N;
+                break;
+            }
             res64 = h64.err;
             for (int i = 0; i < 6; ++i) sav[i] = h64.sig_hat0[i] / (double)N;
-            ++nref;
-            if (ri != RPM_OK) break;
+            // a correction stopped by a stall still lowered the FP64 error
+            if (si.hs.status != 0 && si.hs.status != 4) break;
         }
         if (nref > 0) {
             // the refined FP64 field, rounded, is the result
@@ -1093,7 +1160,8 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
         st->refinements = nref;
     }
     switch (hs_main.status) {
-        case 0: return (refine && !(res64 <= o->tol)) ? RPM_NOT_CONVERGED : RPM_OK;
+        case 0:
+        case 4: return (refine && res64 <= o->tol) || (!refine && hs_main.status == 0) ? RPM_OK : RPM_NOT_CONVERGED;
         case 2: return RPM_DIVERGED;
         case 3: return RPM_SINGULAR;
         default: return RPM_NOT_CONVERGED;
@@ -1128,6 +1196,7 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
         return RPM_E_INVALID;
     if (o->map != RPM_MAP_LS && o->map != RPM_MAP_POLARIZATION) return RPM_E_INVALID;
     if (o->profile_classes < 0 || o->profile_classes >= (1 << RPM_NKERNEL)) return RPM_E_INVALID;
+    if (o->stall_window < 0) return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
         return RPM_E_INVALID;
@@ -1225,6 +1294,14 @@ rpm_status seed_typed(const rpm_problem* pr, const rpm_options* o, const void* V
     T* tmp = c.template at<T>(c.L.tmp);
     T* tmp2 = c.template at<T>(c.L.tmp2);
     double* nr = c.gx() + 4 * kMaxP;
+    Ctx<double> c64;
+    if constexpr (sizeof(T) == 4) {
+        sub64_init(c64, c, o);
+        int p64 = 0;
+        rs = prepare(c64, pr, o, false, &p64, o->tol);
+        if (rs != RPM_OK) return rs;
+        c.sub = &c64;
+    }
     int added = 0, jvps = 0;
     for (int k = 0; k < p0 && p < c.pmax; ++k) {
         const T* v = reinterpret_cast<const T*>(V) + (long long)k * nel;
@@ -1235,6 +1312,17 @@ rpm_status seed_typed(const rpm_problem* pr, const rpm_options* o, const void* V
         double n2 = 0.0;
         if (!sync_read(c, &n2, nr, sizeof(n2))) return RPM_E_HIP;
         if (!(n2 > 0.0) || !finite(n2)) continue;
+        if (c.sub && !c.pol) {
+            // FP32 fields: normalised and projected in FP64
+            Ctx<double>& sd = *c.sub;
+            k_convert<double, double><<<gb, 256, 0, c.s>>>(D1, sd.ring(3), 1.0 / std::sqrt(n2), nel);
+            project_compatible<double>(sd, sd.ring(3), D1);
+            double* cand[1] = {D1};
+            const int r = add_columns<T, 1>(c, p, cand, &jvps);
+            if (r < 0) return RPM_E_HIP;
+            added += r;
+            continue;
+        }
         k_convert<double, T><<<gb, 256, 0, c.s>>>(D1, tmp, 1.0 / std::sqrt(n2), nel);
         if (c.pol) {
             k_convert<T, double><<<gb, 256, 0, c.s>>>(tmp, D1, 1.0, nel);
@@ -1403,6 +1491,7 @@ void rpm_default_options(rpm_options* o)
     o->profile_classes = 0;
     o->alpha = 2.0;
     o->beta = 2.0;
+    o->stall_window = 400;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
@@ -1532,6 +1621,23 @@ rpm_status rpm_workspace_basis_dim(const void* workspace, size_t ws_bytes, int32
         return RPM_E_HIP;
     if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return RPM_E_HIP;
     *p = hs.magic == kStateMagic ? hs.p : 0;
+    return RPM_OK;
+}
+
+rpm_status rpm_workspace_h(const void* workspace, size_t ws_bytes, double* H, int32_t ld, int32_t* p,
+                           void* hip_stream)
+{
+    if (!workspace || !H || !p || ld < 1 || ws_bytes < sizeof(DevState)) return RPM_E_INVALID;
+    DevState hs;
+    if (hipMemcpyAsync(&hs, workspace, sizeof(DevState), hipMemcpyDeviceToHost, (hipStream_t)hip_stream) !=
+        hipSuccess)
+        return RPM_E_HIP;
+    if (hipStreamSynchronize((hipStream_t)hip_stream) != hipSuccess) return RPM_E_HIP;
+    const int pp = hs.magic == kStateMagic ? hs.p : 0;
+    if (pp > ld) return RPM_E_INVALID;
+    for (int i = 0; i < pp; ++i)
+        for (int j = 0; j < pp; ++j) H[(long long)i * ld + j] = hs.H[i * kMaxP + j];
+    *p = pp;
     return RPM_OK;
 }
 
