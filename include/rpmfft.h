@@ -148,6 +148,14 @@ typedef struct {
                                  value for this many iterations (FP32 rounding
                                  floor); refinement then continues from that
                                  field.  0 = never (>= 0)                        */
+    int32_t batch_cases;      /* rpm_fft_effective_tensor with RPM: solve the
+                                 unit load cases together, one pass over the
+                                 basis serving all of them per step (shared Z,
+                                 W, H), growing it from the differences of the
+                                 case with the largest error (1) or of every
+                                 case still iterating, largest error first (2);
+                                 the workspace must be sized with a non-zero
+                                 value.  0 = one case after the other            */
 } rpm_options;
 
 typedef struct {
@@ -175,7 +183,7 @@ typedef struct {
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
  * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
  * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2,
- * no profiling (profile_classes 0), stall_window 400. */
+ * no profiling (profile_classes 0), stall_window 400, batch_cases 0. */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and

@@ -43,7 +43,8 @@ class RpmOptions(ctypes.Structure):
                 ("replay", ctypes.POINTER(ctypes.c_int32)), ("replay_len", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
-                ("profile_classes", ctypes.c_int32), ("stall_window", ctypes.c_int32)]
+                ("profile_classes", ctypes.c_int32), ("stall_window", ctypes.c_int32),
+                ("batch_cases", ctypes.c_int32)]
 
 
 class RpmStats(ctypes.Structure):

@@ -986,7 +986,7 @@ struct Raw4<double> {
 // Up to four field pointers of a product kernel (unused slots null).
 template <typename TA>
 struct Fields {
-    const TA* f[4];
+    const TA* f[6];
 };
 
 // Column-group products (no update): wave g of a block of 64 * ceil(p / 8)
@@ -1643,6 +1643,99 @@ __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi
             for (int j = 0; j < p; ++j) v += dj[j] * Z[zix(i, j, zP)];
             eps[i] = v;
         }
+    }
+}
+
+// Load cases of a batched solve (the unit mean strains of the effective
+// tensor): per case the previous xi, the recombined eps, the Newton
+// coefficients d and the stop flag.
+constexpr int kMaxCases = 6;
+template <typename T>
+struct CasePtrs {
+    const T* xi[kMaxCases];
+    T* eps[kMaxCases];
+    const double* d[kMaxCases];
+    const int* done[kMaxCases];
+};
+
+// Batched recombination eps_f = xi_f + sum_j d_f[j] Z_j for the NB load cases,
+// one pass over the basis for all of them (each column slice is loaded once
+// and applied to every case still iterating); layout and load pattern as
+// k_recombine.
+template <typename T, int NB>
+__global__ __launch_bounds__(kThreads) void k_recombine_multi(CasePtrs<T> cp, const T* __restrict__ Z, int p, int zP,
+                                                              long long n)
+{
+    constexpr int VL = 16 / sizeof(T);
+    using V = typename Vec4<T>::type;
+    __shared__ T dj[NB][kMaxP + 8];
+    __shared__ int act[NB];
+    for (int f = 0; f < NB; ++f)
+        for (int j = threadIdx.x; j < kMaxP + 8; j += kThreads) dj[f][j] = j < p ? (T)cp.d[f][j] : T(0);
+    if (threadIdx.x < NB) act[threadIdx.x] = *cp.done[threadIdx.x] ? 0 : 1;
+    __syncthreads();
+    const long long e = ((long long)blockIdx.x * kThreads + threadIdx.x) * VL;
+    if (e >= n) return;
+    if (e + VL <= n) {
+        V acc[NB];
+#pragma unroll
+        for (int f = 0; f < NB; ++f) {
+            if (act[f]) acc[f] = *reinterpret_cast<const V*>(cp.xi[f] + e);
+            else {
+                T* a = reinterpret_cast<T*>(&acc[f]);
+#pragma unroll
+                for (int q = 0; q < VL; ++q) a[q] = T(0);
+            }
+        }
+        const T* zt = Z + zix(e, 0, zP);
+        for (int g = 0; g < p; g += 8) {
+            V z[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                z[u] = nt_load(reinterpret_cast<const V*>(zt + (long long)min(g + u, p - 1) * kZTile));
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const T* zs = reinterpret_cast<const T*>(&z[u]);
+#pragma unroll
+                for (int f = 0; f < NB; ++f) {
+                    T* a = reinterpret_cast<T*>(&acc[f]);
+                    const T c = dj[f][g + u];
+#pragma unroll
+                    for (int q = 0; q < VL; ++q) a[q] += c * zs[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NB; ++f)
+            if (act[f]) *reinterpret_cast<V*>(cp.eps[f] + e) = acc[f];
+    } else {
+        for (int f = 0; f < NB; ++f) {
+            if (!act[f]) continue;
+            for (long long i = e; i < n; ++i) {
+                T v = cp.xi[f][i];
+                for (int j = 0; j < p; ++j) v += dj[f][j] * Z[zix(i, j, zP)];
+                cp.eps[f][i] = v;
+            }
+        }
+    }
+}
+
+// The basis part of the solver state (p, H, its factorisation and inverse, the
+// Gram matrix) copied from one load case's state to another's after the
+// shared basis grew.
+__global__ __launch_bounds__(kThreads) void k_copy_basis_state(DevState* __restrict__ dst,
+                                                               const DevState* __restrict__ src)
+{
+    for (int e = threadIdx.x; e < kMaxP * kMaxP; e += kThreads) {
+        dst->H[e] = src->H[e];
+        dst->LU[e] = src->LU[e];
+        dst->G[e] = src->G[e];
+        dst->AinvT[e] = src->AinvT[e];
+    }
+    for (int e = threadIdx.x; e < kMaxP; e += kThreads) dst->piv[e] = src->piv[e];
+    if (threadIdx.x == 0) {
+        dst->p = src->p;
+        dst->singular = src->singular;
     }
 }
 

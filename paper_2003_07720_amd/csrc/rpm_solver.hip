@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -209,11 +210,19 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     return s;
 }
 
+// Per-load-case state of a batched solve (case 0 uses the base offsets).
+struct CaseOff {
+    size_t st, pmean, perr, pinc, pdots, sums, gsum, ring[4], eps, hist;
+};
+
 struct Layout {
     size_t st, twx, twy, twr, lame, hist, pmean, perr, pinc, pdots, pg, sums, gsum, gx, ring[4], eps, tmp, tmp2, S1, S2,
         Z, W, D1, D0, shift, sub64, total;
     int ld;
     long long hist_cap;
+    int nb = 0;          // load cases of a batched solve (0: not batched)
+    size_t bpd = 0;      // basis products of the batched projection (nb x kMaxP columns of Gq partials)
+    CaseOff cs[kMaxCases];
 };
 
 rpm_options basic_fp64_options(const rpm_options* o)
@@ -292,9 +301,40 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o, bool map_only)
         const rpm_options b = basic_fp64_options(o);
         off = align_up(off + make_layout<double>(make_shapes<double>(n, spectral_comps(&b)), &b).total);
     }
+    // batched load cases: their own state, partial sums and fields behind
+    // everything a single solve uses (the basis stays where a single solve
+    // keeps it, so the two share a carried basis)
+    if (o->batch_cases && pmax > 0 && !map_only) {
+        L.nb = g.two_d ? 3 : 6;
+        L.bpd = take(sizeof(double) * (size_t)L.nb * kMaxP * s.Gq);
+        for (int f = 1; f < L.nb; ++f) {
+            CaseOff& c = L.cs[f];
+            c.st = take(sizeof(DevState));
+            c.pmean = take(sizeof(double) * 6 * s.G1);
+            c.perr = take(sizeof(double) * s.G3);
+            c.pinc = take(sizeof(double) * s.G1);
+            c.pdots = take(sizeof(double) * 2 * L.ld * std::max(std::max(s.G1, s.Gp), s.Gq));
+            c.sums = take(sizeof(double) * (2 * kMaxP + 8));
+            c.gsum = take(sizeof(double) * (kMaxP + 8));
+            for (int i = 0; i < 4; ++i) c.ring[i] = take(fT);
+            c.eps = take(fT);
+        }
+    }
     // last: its size follows max_iter, which may differ between calls that
     // carry the basis, so nothing the workspace keeps may sit behind it
     L.hist = take(sizeof(double) * L.hist_cap);
+    for (int f = 1; f < L.nb; ++f) L.cs[f].hist = take(sizeof(double) * L.hist_cap);
+    CaseOff& c0 = L.cs[0];
+    c0.st = L.st;
+    c0.pmean = L.pmean;
+    c0.perr = L.perr;
+    c0.pinc = L.pinc;
+    c0.pdots = L.pdots;
+    c0.sums = L.sums;
+    c0.gsum = L.gsum;
+    for (int i = 0; i < 4; ++i) c0.ring[i] = L.ring[i];
+    c0.eps = L.eps;
+    c0.hist = L.hist;
     L.total = off;
     return L;
 }
@@ -1047,41 +1087,20 @@ rpm_status eval64(Ctx<double>& c64, DevState& hs)
 
 // Solve for E and write the caller's outputs; with FP32 fields, certify the
 // result in FP64 and refine it when the FP64 error misses tol.
+// After the iteration: certify an FP32 result in FP64 and refine it while the
+// FP64 error misses tol (c64: the FP64 pipeline, FP32 fields only), then write
+// the caller's outputs and statistics and map the stop reason to a status.
 template <typename T>
-rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const rpm_options* o, const T* eps0,
-                      T* eps_out, T* sig_out, double* sig_avg, rpm_stats* st, bool reuse)
+rpm_status finish_solve(Ctx<T>& c, Ctx<double>& c64, const rpm_problem* pr, const rpm_options* o, SolveOut<T>& so,
+                        T* eps_out, T* sig_out, double* sig_avg, rpm_stats* st,
+                        std::chrono::steady_clock::time_point t0)
 {
-    auto t0 = std::chrono::steady_clock::now();
     const long long N = c.sh.g.N;
     const long long nel = 6 * N;
     const int gb = (int)((nel + 255) / 256);
-    // FP32 fields carry ~1e-7 rounding, so equilibrium errors much below 1e-6 are
-    // not reliably reachable in FP32: with refinement on, the FP32 stage stops at
-    // max(tol, kFp32Stage) and FP64 refinement takes the field to tol.
     const bool refine = sizeof(T) == 4 && o->refine > 0;
-    const double stage_tol = refine ? std::max(o->tol, kFp32Stage) : o->tol;
-    // with refinement, a stalled FP32 stage hands its field over to it
     const int stall = refine ? o->stall_window : 0;
-    // FP32 fields: the FP64 pipeline (JVPs and projections of basis growth,
-    // certification, refinement)
-    Ctx<double> c64;
-    struct SubReset {
-        Ctx<T>& c;
-        ~SubReset() { c.sub = nullptr; }
-    } sub_reset{c};
     rpm_status rs = RPM_OK;
-    if constexpr (sizeof(T) == 4) {
-        sub64_init(c64, c, o);
-        int p64 = 0;
-        rs = prepare(c64, pr, o, false, &p64, o->tol);
-        if (rs != RPM_OK) return rs;
-        set_E(c64, E);
-        c.sub = &c64;
-    }
-    Spec<T> sp{E, eps0, false, nullptr, 0, stage_tol, 1.0, reuse, stall};
-    SolveOut<T> so;
-    rs = run_solve(c, pr, o, sp, so);
-    if (rs < 0) return rs;
     const DevState hs_main = so.hs;
     if (st && st->history && st->history_cap > 0) {  // before correction solves reuse the buffer
         const int n = std::min(st->history_cap, hs_main.iters);
@@ -1159,6 +1178,7 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
         st->residual_fp64 = res64;
         st->refinements = nref;
     }
+    (void)pr;
     switch (hs_main.status) {
         case 0:
         case 4: return (refine && res64 <= o->tol) || (!refine && hs_main.status == 0) ? RPM_OK : RPM_NOT_CONVERGED;
@@ -1166,6 +1186,41 @@ rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const
         case 3: return RPM_SINGULAR;
         default: return RPM_NOT_CONVERGED;
     }
+}
+
+template <typename T>
+rpm_status solve_full(Ctx<T>& c, const rpm_problem* pr, const double E[6], const rpm_options* o, const T* eps0,
+                      T* eps_out, T* sig_out, double* sig_avg, rpm_stats* st, bool reuse)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    // FP32 fields carry ~1e-7 rounding, so equilibrium errors much below 1e-6 are
+    // not reliably reachable in FP32: with refinement on, the FP32 stage stops at
+    // max(tol, kFp32Stage) and FP64 refinement takes the field to tol.
+    const bool refine = sizeof(T) == 4 && o->refine > 0;
+    const double stage_tol = refine ? std::max(o->tol, kFp32Stage) : o->tol;
+    // with refinement, a stalled FP32 stage hands its field over to it
+    const int stall = refine ? o->stall_window : 0;
+    // FP32 fields: the FP64 pipeline (JVPs and projections of basis growth,
+    // certification, refinement)
+    Ctx<double> c64;
+    struct SubReset {
+        Ctx<T>& c;
+        ~SubReset() { c.sub = nullptr; }
+    } sub_reset{c};
+    rpm_status rs = RPM_OK;
+    if constexpr (sizeof(T) == 4) {
+        sub64_init(c64, c, o);
+        int p64 = 0;
+        rs = prepare(c64, pr, o, false, &p64, o->tol);
+        if (rs != RPM_OK) return rs;
+        set_E(c64, E);
+        c.sub = &c64;
+    }
+    Spec<T> sp{E, eps0, false, nullptr, 0, stage_tol, 1.0, reuse, stall};
+    SolveOut<T> so;
+    rs = run_solve(c, pr, o, sp, so);
+    if (rs < 0) return rs;
+    return finish_solve(c, c64, pr, o, so, eps_out, sig_out, sig_avg, st, t0);
 }
 
 bool finite(double x) { return std::isfinite(x); }
@@ -1197,6 +1252,7 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->map != RPM_MAP_LS && o->map != RPM_MAP_POLARIZATION) return RPM_E_INVALID;
     if (o->profile_classes < 0 || o->profile_classes >= (1 << RPM_NKERNEL)) return RPM_E_INVALID;
     if (o->stall_window < 0) return RPM_E_INVALID;
+    if (o->batch_cases < 0 || o->batch_cases > 2) return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
         return RPM_E_INVALID;
@@ -1371,6 +1427,263 @@ rpm_status eff_typed(const rpm_problem* pr, const rpm_options* o, double* C, rpm
     return worst;
 }
 
+// The view of load case f of a batched solve: the shared workspace (spectra,
+// basis, growth temporaries, FP64 pipeline) with the case's own state,
+// partial sums, fields and error history.
+template <typename T>
+void case_ctx(Ctx<T>& cf, const Ctx<T>& c, int f)
+{
+    cf.sh = c.sh;
+    cf.L = c.L;
+    const CaseOff& o = c.L.cs[f];
+    cf.L.st = o.st;
+    cf.L.pmean = o.pmean;
+    cf.L.perr = o.perr;
+    cf.L.pinc = o.pinc;
+    cf.L.pdots = o.pdots;
+    cf.L.sums = o.sums;
+    cf.L.gsum = o.gsum;
+    for (int i = 0; i < 4; ++i) cf.L.ring[i] = o.ring[i];
+    cf.L.eps = o.eps;
+    cf.L.hist = o.hist;
+    cf.s = c.s;
+    cf.ws = c.ws;
+    cf.st = reinterpret_cast<DevState*>(c.ws + o.st);
+    cf.phase = c.phase;
+    cf.lam0 = c.lam0;
+    cf.mu0 = c.mu0;
+    cf.pmax = c.pmax;
+    cf.pol = c.pol;
+    cf.alpha = c.alpha;
+    cf.beta = c.beta;
+    cf.prof.on = false;
+    cf.sub = c.sub;
+}
+
+// Stop flags of a state (the prefix of DevState up to and including err).
+struct StateHead {
+    int done, status, iters;
+    double err;
+};
+
+template <typename T>
+bool read_head(Ctx<T>& c, StateHead& h)
+{
+    DevState hs;
+    const size_t n = offsetof(DevState, err) + sizeof(double);
+    if (hipMemcpyAsync(&hs, c.st, n, hipMemcpyDeviceToHost, c.s) != hipSuccess) return false;
+    if (hipStreamSynchronize(c.s) != hipSuccess) return false;
+    h.done = hs.done;
+    h.status = hs.status;
+    h.iters = hs.iters;
+    h.err = hs.err;
+    return !c.hip_error;
+}
+
+template <typename T, int NB>
+void launch_recombine_multi(Ctx<T>& c, const CasePtrs<T>& cp, int p)
+{
+    const long long nel = 6 * c.sh.g.N;
+    const int VL = 16 / (int)sizeof(T);
+    const int gb = (int)((nel / VL + kThreads - 1) / kThreads) + 1;
+    k_recombine_multi<T, NB><<<gb, kThreads, 0, c.s>>>(cp, c.Zb(), p, c.pmax, nel);
+}
+
+// Effective tensor with the load cases solved together (Algorithm 2 for every
+// unit mean strain at once): each step recombines every case from one pass
+// over the basis, applies the map to each case, and projects every case on
+// the basis in one more pass, so the basis streams (the bulk of an RPM step's
+// bytes) are read once for all cases instead of once per case.  The cases
+// share Z, W and H (F_u does not depend on E); the basis grows from the
+// differences of the case with the largest error.  FP32 results are then
+// certified and refined case by case.
+template <typename T>
+rpm_status eff_batched(const rpm_problem* pr, const rpm_options* o, double* C, rpm_stats* stv, void* ws,
+                       size_t ws_bytes, void* stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, o, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    const int nb = c.L.nb;
+    const bool two_d = pr->n[2] == 1;
+    const int cases3[3] = {0, 1, 5};
+    const Geo& g = c.sh.g;
+    const long long N = g.N;
+    const bool refine = sizeof(T) == 4 && o->refine > 0;
+    const double stage_tol = refine ? std::max(o->tol, kFp32Stage) : o->tol;
+    const int stall = refine ? o->stall_window : 0;
+    Ctx<double> c64;
+    if constexpr (sizeof(T) == 4) {
+        sub64_init(c64, c, o);
+        int p64 = 0;
+        rs = prepare(c64, pr, o, false, &p64, o->tol);
+        if (rs != RPM_OK) return rs;
+        c.sub = &c64;
+    }
+    Ctx<T> cx[kMaxCases];
+    double Ec[kMaxCases][6];
+    int p = 0;
+    for (int f = 0; f < nb; ++f) {
+        case_ctx(cx[f], c, f);
+        const int j = two_d ? cases3[f] : f;
+        for (int i = 0; i < 6; ++i) Ec[f][i] = 0.0;
+        Ec[f][j] = j < 3 ? 1.0 : 0.5;
+        int pf = 0;
+        rs = prepare(cx[f], pr, o, f == 0 && o->reuse_basis != 0, &pf, stage_tol, 1.0, stall);
+        if (rs != RPM_OK) return rs;
+        if (f == 0) p = pf;
+        set_E(cx[f], Ec[f]);
+    }
+    // a carried basis (case 0's state) serves every case
+    for (int f = 1; f < nb && p > 0; ++f) k_copy_basis_state<<<1, kThreads, 0, c.s>>>(cx[f].st, cx[0].st);
+
+    const int* done[kMaxCases];
+    for (int f = 0; f < nb; ++f) done[f] = &cx[f].st->done;
+    // start: eps = E_f, xi = F(eps), projections and Newton step per case
+    for (int f = 0; f < nb; ++f) {
+        k_fill_uniform<T><<<(int)((6 * N + 255) / 256), 256, 0, c.s>>>(cx[f].eps(), cx[f].st->E, N);
+        run_F<T>(cx[f], cx[f].eps(), 0, nullptr, cx[f].eps(), cx[f].ring(1), OUT_XI, 0, DC_MEAN, cx[f].st->E,
+                 done[f]);
+        if (p > 0) project(cx[f], cx[f].ring(1), cx[f].eps(), p, true);
+        reduce_and_finalize(cx[f], p, 1, 0, true, done[f]);
+    }
+    int it = 1, nu = 0, nq = 0, jvps = 0, growth = 0;
+    std::vector<int> decisions;
+    int p_end[kMaxCases];
+    bool seen_done[kMaxCases] = {false, false, false, false, false, false};
+    const int check = std::max(1, o->check_every);
+    for (;;) {
+        const bool at_growth = (nu > o->n_max) && p < c.pmax;
+        if (at_growth || (it % check) == 0 || it >= o->max_iter) {
+            bool all = true;
+            int worst = -1;
+            double werr = -1.0;
+            double herr[kMaxCases];
+            for (int f = 0; f < nb; ++f) {
+                StateHead h;
+                if (!read_head(cx[f], h)) return RPM_E_HIP;
+                herr[f] = h.err;
+                const bool d = h.done || h.iters >= o->max_iter;
+                if (d && !seen_done[f]) {
+                    seen_done[f] = true;
+                    p_end[f] = p;
+                }
+                if (!d) {
+                    all = false;
+                    if (h.err > werr) {
+                        werr = h.err;
+                        worst = f;
+                    }
+                }
+            }
+            if (all) break;
+            if (at_growth) {
+                const int p_before = p;
+                // batch_cases 1: the differences of the case with the largest
+                // error; 2: of every case still iterating, largest error first
+                int order[kMaxCases], no = 0;
+                order[no++] = worst;
+                if (o->batch_cases == 2) {
+                    for (int f = 0; f < nb; ++f)
+                        if (!seen_done[f] && f != worst) order[no++] = f;
+                    std::sort(order + 1, order + no, [&](int a, int b) { return herr[a] > herr[b]; });
+                }
+                int last = worst;
+                for (int k = 0; k < no && p < c.pmax; ++k) {
+                    const int f = order[k];
+                    if (f != last) k_copy_basis_state<<<1, kThreads, 0, c.s>>>(cx[f].st, cx[last].st);
+                    int want = 0;
+                    const int added = grow_basis(cx[f], it, nq, p, o, (int)decisions.size(), &want, &jvps);
+                    if (added < 0) return RPM_E_HIP;
+                    decisions.push_back(want);
+                    last = f;
+                }
+                ++growth;
+                nu = 0;
+                nq = 0;
+                for (int f = 0; f < nb; ++f) {
+                    if (f != last) k_copy_basis_state<<<1, kThreads, 0, c.s>>>(cx[f].st, cx[last].st);
+                    const T* cur = (p_before > 0 || it == 1) ? cx[f].eps() : cx[f].ring(it - 1);
+                    project(cx[f], cx[f].ring(it), cur, p, true);
+                    reduce_and_finalize(cx[f], p, it, 1, true, done[f]);
+                }
+            }
+        }
+        ++it;
+        if (p > 0) {
+            CasePtrs<T> cp{};
+            for (int f = 0; f < nb; ++f) {
+                cp.xi[f] = cx[f].ring(it - 1);
+                cp.eps[f] = cx[f].eps();
+                cp.d[f] = cx[f].st->d;
+                cp.done[f] = done[f];
+            }
+            hipEvent_t ev;
+            c.mark_begin(RPM_K_RECOMBINE, ev);
+            if (nb == 6) launch_recombine_multi<T, 6>(c, cp, p);
+            else launch_recombine_multi<T, 3>(c, cp, p);
+            c.mark_end(RPM_K_RECOMBINE, ev, 6.0 * (double)N * sizeof(T) * (2 * nb + p));
+        }
+        for (int f = 0; f < nb; ++f) {
+            const T* in = p > 0 ? cx[f].eps() : cx[f].ring(it - 1);
+            run_F<T>(cx[f], in, 0, nullptr, in, cx[f].ring(it), OUT_XI, 0, DC_MEAN, cx[f].st->E, done[f]);
+        }
+        if (p > 0) {
+            // zeta_j of every case in one pass over the basis: case f's products at
+            // bpd + f kMaxP Gq (column j at + j Gq)
+            Fields<T> fl{};
+            for (int f = 0; f < nb; ++f) fl.f[f] = cx[f].ring(it);
+            double* bpd = c.template at<double>(c.L.bpd);
+            hipEvent_t ev;
+            c.mark_begin(RPM_K_PROJECT, ev);
+            if (nb == 6) launch_gdots<T, T, 6, 0>(c.s, c.sh.Gq, fl, c.Zb(), p, c.pmax, N, bpd, kMaxP);
+            else launch_gdots<T, T, 3, 0>(c.s, c.sh.Gq, fl, c.Zb(), p, c.pmax, N, bpd, kMaxP);
+            c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)N * sizeof(T) * (nb + p));
+        }
+        for (int f = 0; f < nb; ++f) {
+            const double* bpd = c.template at<double>(c.L.bpd) + (long long)f * kMaxP * c.sh.Gq;
+            k_reduce_main<<<1 + p, kThreads, 0, c.s>>>(cx[f].template at<double>(cx[f].L.perr), c.sh.G3, bpd,
+                                                       c.sh.Gq, kMaxP, p, cx[f].sums(), done[f]);
+            k_step_end<<<1, kThreads, 0, c.s>>>(cx[f].st, cx[f].sums(), p, it & 3, g.two_d, 0, 0, 0,
+                                                cx[f].template at<double>(cx[f].L.hist), (int)c.L.hist_cap);
+        }
+        c.check_launch();
+        ++nu;
+        ++nq;
+    }
+    for (int f = 0; f < nb; ++f)
+        if (!seen_done[f]) p_end[f] = p;
+    // per case: the returned iterate, FP64 certification / refinement, outputs
+    rpm_status worst = RPM_OK;
+    for (int f = 0; f < nb; ++f) {
+        SolveOut<T> so;
+        if (!sync_read(cx[f], &so.hs, cx[f].st, sizeof(DevState))) return RPM_E_HIP;
+        const int itf = std::max(so.hs.iters, 1);
+        so.final_it = (itf == 1 || p_end[f] > 0) ? cx[f].eps() : cx[f].ring(itf - 1);
+        so.jvps = f == 0 ? jvps : 0;
+        so.growth = growth;
+        so.p = p;
+        so.decisions = decisions;
+        if constexpr (sizeof(T) == 4) set_E(c64, Ec[f]);
+        double sav[6];
+        rs = finish_solve<T>(cx[f], c64, pr, o, so, nullptr, nullptr, sav, stv ? stv + f : nullptr, t0);
+        if (rs < 0) return rs;
+        if (rs != RPM_OK && worst == RPM_OK) worst = rs;
+        for (int row = 0; row < nb; ++row) C[row * nb + f] = sav[two_d ? cases3[row] : row];
+    }
+    if (c.prof.on) {
+        c.prof.harvest();
+        if (stv)
+            for (int k = 0; k < RPM_NKERNEL; ++k) {
+                stv[0].kernel_ms[k] += c.prof.ms[k];
+                stv[0].kernel_launches[k] += c.prof.n[k];
+                stv[0].kernel_bytes[k] += c.prof.bytes[k];
+            }
+    }
+    return worst;
+}
+
 // Prescribed mean stress (the cell problem "given the average strain or
 // stress" of Sec. 2): the effective stiffness from one solve per unit mean
 // strain (the basis carried from case to case), the mean strain E with
@@ -1492,6 +1805,7 @@ void rpm_default_options(rpm_options* o)
     o->alpha = 2.0;
     o->beta = 2.0;
     o->stall_window = 400;
+    o->batch_cases = 0;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
@@ -1585,6 +1899,10 @@ rpm_status rpm_fft_effective_tensor(const rpm_problem* pr, const rpm_options* o,
     rpm_status rs = validate(pr, o);
     if (rs != RPM_OK) return rs;
     if (!C_eff) return RPM_E_INVALID;
+    if (o->batch_cases && o->scheme == RPM_SCHEME_RPM && o->p_max > 0) {
+        if (o->precision == RPM_FP64) return eff_batched<double>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
+        return eff_batched<float>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
+    }
     if (o->precision == RPM_FP64) return eff_typed<double>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
     return eff_typed<float>(pr, o, C_eff, st, workspace, ws_bytes, hip_stream);
 }

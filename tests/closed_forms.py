@@ -244,3 +244,64 @@ def iso_projection(Cv):
     iijj = Cv[:3, :3].sum()
     ijij = np.trace(Cv[:3, :3]) + 2.0 * np.trace(Cv[3:, 3:])
     return iijj / 9.0, (ijij - iijj / 3.0) / 10.0
+
+
+# ---------------------------------------------------------------------------
+# Growth pin: a two-phase laminate along z whose iterate error lies in two known
+# eigenvectors of the linear part of the map.
+#
+# With layers normal to n = e_z, a compatible zero-mean field that depends on z
+# only and has the single shear component eps_xz = a(z)/2 is mapped by F_u to
+# the field of the same kind with a -> (1 - m) a + <m a>, m = mu(z)/mu0 (the
+# Green operator at k parallel to e_z takes the traction mu a).  A profile a
+# supported on the layers of one phase with zero mean there is therefore an
+# eigenvector with eigenvalue 1 - m of that phase.  Starting from
+# eps* + c1 v1 + c2 v2 (v1 in phase A, v2 in phase B), the fixed point gives
+# xi^(j) = eps* + sum_i c_i lam_i^(j+1) v_i, so the two differences of q that
+# feed the growth after n_max + 1 steps are known in closed form.
+
+def laminate_growth_case(n_xy=4, nz=8, n_a=3, lam=(0.9, -0.5), mu0=1.0, nu=0.3):
+    """Phase map (nz, n_xy, n_xy) with phase 0 on the first n_a layers, Lame table
+    whose shear moduli give F_u the eigenvalues lam on the two profiles, the
+    reference medium, and the unit-norm (Frobenius) eigenvector fields v1, v2."""
+    ph = np.ones((nz, n_xy, n_xy), dtype=np.uint8)
+    ph[:n_a] = 0
+    E0 = 2.0 * (1.0 + nu) * mu0
+    phases = [(E0 * (1.0 - l), nu) for l in lam]  # mu_i / mu0 = 1 - lam_i (equal nu)
+    lame_tab = [lame(E, nu) for E, nu in phases]
+    prof_a = np.zeros(nz)
+    prof_a[0], prof_a[1] = 1.0, -1.0              # zero mean over phase 0's layers
+    prof_b = np.zeros(nz)
+    prof_b[n_a], prof_b[n_a + 2], prof_b[nz - 1] = 2.0, -1.0, -1.0  # zero mean over phase 1's layers
+    vs = []
+    for prof in (prof_a, prof_b):
+        v = np.zeros((6, nz, n_xy, n_xy))
+        v[4] = 0.5 * prof[:, None, None]          # eps_xz = a/2
+        vs.append(v / np.sqrt(frob(v, v)))
+    return ph, lame_tab, lame(E0, nu), vs[0], vs[1]
+
+
+def frob(a, b):
+    """Frobenius inner product of two [6][...] tensor fields (shear weighted 2)."""
+    w = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
+    return float(np.sum(w[:, None] * a.reshape(6, -1) * b.reshape(6, -1)))
+
+
+def growth_ratio(c, lam, n_max):
+    """T22 / T11 of the QR of [dq^(n), dq^(n-1)], n = n_max, for the iterate error
+    c1 v1 + c2 v2 (unit, orthogonal v_i): dq^(n) = sum c_i lam_i^n (lam_i - 1) v_i,
+    dq^(n-1) = sum c_i lam_i^(n-1) (lam_i - 1) v_i."""
+    a = np.array([ci * li ** n_max * (li - 1.0) for ci, li in zip(c, lam)])
+    b = a / np.array(lam)
+    T11 = np.linalg.norm(a)
+    T22 = abs(a[0] * b[1] - a[1] * b[0]) / T11
+    return T22 / T11
+
+
+def coefficient_for_ratio(rho, lam, n_max, c1=1.0):
+    """c2 such that growth_ratio((c1, c2)) = rho (the smaller root)."""
+    g = abs(1.0 / lam[1] - 1.0 / lam[0])
+    # rho = g x / (1 + x^2), x = a2 / a1
+    x = (g - np.sqrt(g * g - 4.0 * rho * rho)) / (2.0 * rho)
+    a1 = c1 * lam[0] ** n_max * (lam[0] - 1.0)
+    return x * a1 / (lam[1] ** n_max * (lam[1] - 1.0))

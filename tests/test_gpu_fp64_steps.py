@@ -72,7 +72,7 @@ def test_seeded_h_matches_oracle_at_contrast_1000(B, prec):
 def test_fp32_stall_hands_over_to_refinement_effective_tensor(B):
     """32^3 stiff spheres at contrast 1000 (E0 = the stiff modulus): the FP32 stage
     stalls above its target, refinement takes every load case to an
-    FP64-certified 1e-6, and C_eff matches the oracle's (tol 1e-9) within 1e-6."""
+    FP64-certified 1e-6, and C_eff matches the oracle's (tol 1e-8) within 1e-6."""
     ph, phases, ref, Cref = _golden("spheres32_contrast1000")
     lt = np.array([B.lame_from_young(*p) for p in phases])
     opts = B.make_options(precision="fp32", tol=1e-6, max_iter=20000, refine=6, check_every=32)
@@ -89,11 +89,11 @@ def test_fp32_stall_hands_over_to_refinement_effective_tensor(B):
 def test_fp32_void_cell_to_1e6_against_oracle(B):
     """32^3 void cell (30 % spherical pores, radii 1.5-3, stiffness 1e-3 of the
     matrix, E0 = the matrix modulus), uniaxial eps_zz: FP32 fields refined to an
-    FP64-certified 1e-6 against the oracle's solve to 1e-9 -- stress field and
+    FP64-certified 1e-6 against the oracle's solve to 1e-7 -- stress field and
     <sigma> -- and the effective tensor against the oracle's."""
     ph, phases, ref, Cref = _golden("voids32_contrast1e-3")
     lt_o = O.lame_table(phases)
-    r = O.solve(ph, lt_o, O.lame(*ref), EZZ, scheme="rpm", tol=1e-9, max_iter=20000, n_max=10, p_max=32)
+    r = O.solve(ph, lt_o, O.lame(*ref), EZZ, scheme="rpm", tol=1e-7, max_iter=20000, n_max=10, p_max=32)
     assert r["status"] == "converged"
     sig_ref = O.stress(ph, lt_o, r["eps"])
     lt = np.array([B.lame_from_young(*p) for p in phases])

@@ -210,3 +210,33 @@ def test_deterministic(B):
     assert a["iterations"] == b["iterations"]
     assert bool((a["eps"] == b["eps"]).all())
     assert np.array_equal(a["history"], b["history"])
+
+
+@pytest.mark.parametrize("kappa,want", [(0.10, 2), (0.15, 1)])
+def test_growth_step_closed_form_gpu(B, kappa, want):
+    """The closed-form growth case of the oracle pins (laminate, error in two
+    eigenvectors of F_u with eigenvalues 0.9 and -0.5, T22/T11 = 0.12): the GPU
+    takes the same decision without replay, H has the eigenvalues 0.9 and -0.5
+    when both columns enter, and Newton lands on the exact laminate solution in
+    one step."""
+    import torch
+
+    lam = (0.9, -0.5)
+    n_max = 4
+    ph, lt, l0, v1, v2 = CF.laminate_growth_case(lam=lam)
+    c1 = 0.01
+    c2 = CF.coefficient_for_ratio(0.12, lam, n_max, c1)
+    E = np.array([0, 0, 0, 0, 0.01, 0])
+    eps_star, _ = CF.laminate_solution(ph, lt, E, axis=2)
+    eps0 = dev(eps_star + c1 * v1 + c2 * v2, torch.float64).contiguous()
+    opts = B.make_options(tol=1e-12, max_iter=n_max + 3, n_max=n_max, p_max=4, kappa=kappa, precision="fp64",
+                          check_every=1)
+    g = B.fft_solve(dev(ph), np.array(lt), l0, E, opts, eps0=eps0)
+    assert list(g["decisions"]) == [want] and g["basis_dim"] == want
+    if want == 2:
+        H = B.workspace_h(g["workspace"])
+        assert np.allclose(np.sort(np.linalg.eigvals(H).real), np.sort(lam), atol=1e-12, rtol=0)
+        assert g["status"] == "RPM_OK" and g["iterations"] == n_max + 3
+        assert np.abs(g["eps"].cpu().numpy() - eps_star).max() < 1e-13
+    else:
+        assert g["status"] == "RPM_NOT_CONVERGED"

@@ -587,3 +587,53 @@ def test_polarization_laminate_exact():
     assert r["status"] == "converged"
     np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
     np.testing.assert_allclose(r["sig_avg"], ref_sig, atol=1e-12)
+
+
+# ------------------------------------------------------------ growth pin
+
+@pytest.mark.parametrize("kappa,want", [(0.10, 2), (0.15, 1)])
+def test_growth_step_closed_form(kappa, want):
+    """In(q, Z) of Sec. 3 / Algorithm 2 on a laminate whose error lies in two known
+    eigenvectors v1, v2 of F_u (eigenvalues 0.9 and -0.5): the differences of q
+    feeding the QR after n_max + 1 steps are known, so T22/T11 is set to 0.12.
+    With kappa = 0.1 two columns are added, they span {v1, v2}, H has the
+    eigenvalues 0.9 and -0.5, and the next Newton step lands on the exact
+    laminate solution; with kappa = 0.15 one column is added (the decision
+    T22 <= kappa T11 taken in that direction, on those differences)."""
+    lam = (0.9, -0.5)
+    n_max = 4
+    ph, lt, l0, v1, v2 = CF.laminate_growth_case(lam=lam)
+    c1 = 0.01
+    c2 = CF.coefficient_for_ratio(0.12, lam, n_max, c1)
+    assert abs(CF.growth_ratio((c1, c2), lam, n_max) - 0.12) < 1e-12
+    E = np.array([0, 0, 0, 0, 0.01, 0])
+    eps_star, sav_star = CF.laminate_solution(ph, lt, E, axis=2)
+    eps0 = eps_star + c1 * v1 + c2 * v2
+    # the two profiles are eigenvectors of F_u = F(.; 0)
+    for v, l in ((v1, lam[0]), (v2, lam[1])):
+        fv, _, _, _ = O.fmap(ph, lt, l0, np.zeros(6), v)
+        assert np.abs(fv - l * v).max() < 1e-14
+    r = O.solve(ph, lt, l0, E, scheme="rpm", tol=1e-12, max_iter=n_max + 3, n_max=n_max, p_max=4, kappa=kappa,
+                eps_init=eps0)
+    assert list(r["decisions"]) == [want]
+    assert r["p"] == want
+    Z = r["basis"].Z[:want].reshape(want, -1)
+    span = np.stack([v1.ravel(), v2.ravel()])
+    w = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])
+    Wf = np.repeat(w, ph.size)
+    # coordinates of each column in the (Frobenius-orthonormal) pair v1, v2
+    coords = (Z * Wf) @ span.T
+    resid = Z - coords @ span
+    assert np.abs(resid).max() < 1e-12
+    if want == 2:
+        H = r["basis"].H[:2, :2]
+        assert np.allclose(np.sort(np.linalg.eigvals(H).real), np.sort(lam), atol=1e-12, rtol=0)
+        # Newton on the invariant span lands on the exact solution in one step
+        assert r["status"] == "converged" and r["iterations"] == n_max + 3
+        assert np.abs(r["eps"] - eps_star).max() < 1e-13
+    else:
+        # one column: the dominant direction dq^(n) (coefficients a_i), not invariant
+        a = np.array([ci * li ** n_max * (li - 1.0) for ci, li in zip((c1, c2), lam)])
+        a /= np.linalg.norm(a)
+        assert np.abs(np.abs(coords[0]) - np.abs(a)).max() < 1e-12
+        assert r["status"] == "not_converged"
