@@ -502,40 +502,59 @@ def time_to_tol(a, B, M, torch, phase, lt, l0, E, common, ws):
 
 
 def disk32_row(B, M, torch):
-    """The 32^2 disk (basic and RPM to 1e-8, FP64) and one load case of the 64^3
-    spheres (E0 at the stiff modulus, RPM to 1e-6, FP64 and FP32 refined) on the
-    GPU, timed after an untimed run of the same call."""
+    """The smaller configurations on the GPU, each timed after an untimed run of
+    the same call, on a side stream so that iterations can be replayed from
+    captured graphs: the 32^2 disk (basic and RPM to 1e-8, FP64; kernel by kernel
+    and from graphs), one load case of the 64^3 spheres (E0 at the stiff
+    modulus, RPM to 1e-6, FP64 and FP32 refined, basis cap 32 and 64) and their
+    6 x 6 effective tensor (load cases one after the other, and batched on one
+    shared basis)."""
     out = {}
-    w = M.workload_disk32()
-    ph = torch.from_numpy(w["phase"]).to("cuda")
-    lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
-    l0 = B.lame_from_young(*w["ref"])
-    for scheme in ("basic", "rpm"):
-        o = B.make_options(scheme=scheme, tol=w["tol"], max_iter=20000, precision="fp64", check_every=32)
-        B.fft_solve(ph, lt, l0, w["E"], o, want_eps=False)
-        torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+
+    def timed(fn):
+        fn()
+        side.synchronize()
         t0 = time.perf_counter()
-        r = B.fft_solve(ph, lt, l0, w["E"], o, want_eps=False)
-        torch.cuda.synchronize()
-        out["disk32_" + scheme] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"],
-                                       seconds=round(time.perf_counter() - t0, 5))
-    s = M.workload_spheres64()
-    ph = torch.from_numpy(s["phase"]).to("cuda")
-    lt = np.array([B.lame_from_young(*p) for p in s["phases"]])
-    l0 = B.lame_from_young(*s["ref"])
-    Ezz = np.array([0, 0, 0.01, 0, 0, 0.0])
-    for prec in ("fp64", "fp32"):
-        o = B.make_options(scheme="rpm", tol=1e-6, max_iter=20000, precision=prec, check_every=32)
-        ws = B.make_workspace(tuple(ph.shape), o)
-        B.fft_solve(ph, lt, l0, Ezz, o, workspace=ws, want_eps=False)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = B.fft_solve(ph, lt, l0, Ezz, o, workspace=ws, want_eps=False)
-        torch.cuda.synchronize()
-        out[f"spheres64_zz_{prec}"] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"],
-                                           map_applications=r["iterations"] + r["jvps"],
-                                           refinements=r["refinements"], residual_fp64=r["residual_fp64"],
-                                           seconds=round(time.perf_counter() - t0, 4))
+        r = fn()
+        side.synchronize()
+        return r, time.perf_counter() - t0
+
+    with torch.cuda.stream(side):
+        w = M.workload_disk32()
+        ph = torch.from_numpy(w["phase"]).to("cuda")
+        lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
+        l0 = B.lame_from_young(*w["ref"])
+        for scheme in ("basic", "rpm"):
+            for graph in (0, 1):
+                o = B.make_options(scheme=scheme, tol=w["tol"], max_iter=20000, precision="fp64", check_every=32,
+                                   graph=graph)
+                ws = B.make_workspace(tuple(ph.shape), o)
+                r, el = timed(lambda: B.fft_solve(ph, lt, l0, w["E"], o, workspace=ws, want_eps=False))
+                out[f"disk32_{scheme}" + ("_graph" if graph else "")] = dict(
+                    status=r["status"], iterations=r["iterations"], jvps=r["jvps"], seconds=round(el, 5))
+        s = M.workload_spheres64()
+        ph = torch.from_numpy(s["phase"]).to("cuda")
+        lt = np.array([B.lame_from_young(*p) for p in s["phases"]])
+        l0 = B.lame_from_young(*s["ref"])
+        Ezz = np.array([0, 0, 0.01, 0, 0, 0.0])
+        for prec, p_max in (("fp64", 32), ("fp32", 32), ("fp64", 64)):
+            o = B.make_options(scheme="rpm", tol=1e-6, max_iter=20000, precision=prec, check_every=32, p_max=p_max,
+                               graph=1)
+            ws = B.make_workspace(tuple(ph.shape), o)
+            r, el = timed(lambda: B.fft_solve(ph, lt, l0, Ezz, o, workspace=ws, want_eps=False))
+            out[f"spheres64_zz_{prec}" + ("" if p_max == 32 else f"_p{p_max}")] = dict(
+                status=r["status"], iterations=r["iterations"], jvps=r["jvps"],
+                map_applications=r["iterations"] + r["jvps"], refinements=r["refinements"],
+                residual_fp64=r["residual_fp64"], seconds=round(el, 4))
+        for batch, p_max in ((0, 32), (0, 64), (1, 64)):
+            o = B.make_options(scheme="rpm", tol=1e-6, max_iter=20000, precision="fp64", check_every=32,
+                               p_max=p_max, batch_cases=batch, graph=1)
+            ws = B.make_workspace(tuple(ph.shape), o)
+            (C, stats, st), el = timed(lambda: B.effective_tensor(ph, lt, l0, o, workspace=ws))
+            out[f"spheres64_ceff_fp64_p{p_max}" + ("_batched" if batch else "")] = dict(
+                status=st, seconds=round(el, 4), iterations=[x["iterations"] for x in stats],
+                jvps=sum(x["jvps"] for x in stats), C11=C[0][0], C33=C[2][2])
     print(f"bench: small configurations {out}", file=sys.stderr, flush=True)
     return out
 

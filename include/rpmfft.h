@@ -156,6 +156,11 @@ typedef struct {
                                  case still iterating, largest error first (2);
                                  the workspace must be sized with a non-zero
                                  value.  0 = one case after the other            */
+    int32_t graph;            /* 1 = launch each main-loop iteration as a
+                                 captured HIP graph (one per ring slot,
+                                 recaptured when the basis grows; ignored with
+                                 profile = 1 or a NULL stream, which cannot be
+                                 captured); 0 = kernel by kernel                 */
 } rpm_options;
 
 typedef struct {
@@ -183,7 +188,7 @@ typedef struct {
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
  * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
  * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2,
- * no profiling (profile_classes 0), stall_window 400, batch_cases 0. */
+ * no profiling (profile_classes 0), stall_window 400, batch_cases 0, graph 0. */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and

@@ -966,6 +966,22 @@ struct Spec {
     int stall;            // stall window of the error (0 = off)
 };
 
+// Captured graphs of one iteration, one per ring slot, for the basis size p.
+struct StepGraphs {
+    bool on = false;
+    int p = -1;
+    hipGraphExec_t ex[4] = {nullptr, nullptr, nullptr, nullptr};
+    void clear()
+    {
+        for (auto& e : ex)
+            if (e) {
+                hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+    }
+    ~StepGraphs() { clear(); }
+};
+
 template <typename T>
 struct SolveOut {
     const T* final_it = nullptr;  // the iterate whose error was evaluated last
@@ -1003,6 +1019,10 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
 
     int it = 1, nu = 0, nq = 0;
     const int check = std::max(1, o->check_every);
+    // iterations replayed from captured graphs (not with profiling events, not
+    // on the legacy default stream, which cannot be captured)
+    StepGraphs graphs;
+    graphs.on = o->graph != 0 && !c.prof.on && c.s != nullptr;
     for (;;) {
         const bool at_growth = rpm && (nu > o->n_max) && p < c.pmax;
         if (at_growth || (it % check) == 0 || it >= o->max_iter) {
@@ -1028,14 +1048,41 @@ rpm_status run_solve(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, con
         // one RPM iteration: eps = xi + Z d, xi = F(eps), Newton step (while
         // the basis is empty eps = xi_prev, read where it lies)
         ++it;
-        const T* xprev = c.ring(it - 1);
-        if (rpm && p > 0) {
-            run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
-            project(c, c.ring(it), c.eps(), p, false);
+        auto step = [&](int i) {
+            const T* xprev = c.ring(i - 1);
+            if (rpm && p > 0) {
+                run_F<T>(c, xprev, p, c.eps(), c.eps(), c.ring(i), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
+                project(c, c.ring(i), c.eps(), p, false);
+            } else {
+                run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(i), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
+            }
+            reduce_and_finalize(c, rpm ? p : 0, i, 0, false, done, sp.err_mode);
+        };
+        if (graphs.on) {
+            // the kernels of an iteration depend on it only through the ring slot
+            // it & 3 (and on the basis size): one graph per slot, recaptured when
+            // the basis grows
+            if (graphs.p != p) {
+                graphs.clear();
+                graphs.p = p;
+            }
+            hipGraphExec_t& ex = graphs.ex[it & 3];
+            if (!ex) {
+                hipGraph_t gr = nullptr;
+                if (hipStreamBeginCapture(c.s, hipStreamCaptureModeThreadLocal) != hipSuccess) return RPM_E_HIP;
+                step(it);
+                if (hipStreamEndCapture(c.s, &gr) != hipSuccess || !gr) return RPM_E_HIP;
+                const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                hipGraphDestroy(gr);
+                if (ie != hipSuccess) {
+                    ex = nullptr;
+                    return RPM_E_HIP;
+                }
+            }
+            if (hipGraphLaunch(ex, c.s) != hipSuccess) return RPM_E_HIP;
         } else {
-            run_F<T>(c, xprev, 0, nullptr, xprev, c.ring(it), OUT_XI, 0, DC_MEAN, c.st->E, done, sp.shift, pinc);
+            step(it);
         }
-        reduce_and_finalize(c, rpm ? p : 0, it, 0, false, done, sp.err_mode);
         ++nu;
         ++nq;
     }
@@ -1253,6 +1300,7 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->profile_classes < 0 || o->profile_classes >= (1 << RPM_NKERNEL)) return RPM_E_INVALID;
     if (o->stall_window < 0) return RPM_E_INVALID;
     if (o->batch_cases < 0 || o->batch_cases > 2) return RPM_E_INVALID;
+    if (o->graph != 0 && o->graph != 1) return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
         return RPM_E_INVALID;
@@ -1806,6 +1854,7 @@ void rpm_default_options(rpm_options* o)
     o->beta = 2.0;
     o->stall_window = 400;
     o->batch_cases = 0;
+    o->graph = 0;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
