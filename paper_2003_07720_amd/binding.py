@@ -82,6 +82,9 @@ for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_ff
            "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress", "rpm_workspace_h"):
     getattr(_lib, _f).restype = ctypes.c_int
 
+EXPORTED_FNO = ["rpm_gemm_bf16", "rpm_fno_param_count", "rpm_fno_workspace_size", "rpm_fno_init", "rpm_fno_forward",
+                "rpm_fno_backward", "rpm_fno_train_step", "rpm_fno_features", "rpm_fno_warm_start"]
+
 EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply",
             "rpm_fft_apply_static", "rpm_fft_solve",
             "rpm_fft_effective_tensor", "rpm_fft_solve_stress", "rpm_fft_seed_basis", "rpm_workspace_basis_dim",
@@ -360,3 +363,140 @@ def workspace_h(workspace):
     if rc != 0:
         raise RpmError(rc, "rpm_workspace_h")
     return H[:p.value, :p.value].copy()
+
+
+# --------------------------------------------------------------------------- learned warm start (rpmfno.h)
+
+class FnoConfig(ctypes.Structure):
+    _fields_ = [("c_in", ctypes.c_int32), ("c_out", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("layers", ctypes.c_int32), ("modes", ctypes.c_int32)]
+
+
+_i64p = _P(ctypes.c_int64)
+_fp = _vp
+_lib.rpm_gemm_bf16.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _i64p, _vp, _i64p,
+                               _vp, _i64p, ctypes.c_float, ctypes.c_float, _vp]
+_lib.rpm_fno_param_count.argtypes = [_P(FnoConfig), _i64p]
+_lib.rpm_fno_workspace_size.argtypes = [_P(FnoConfig), _P(ctypes.c_int32), ctypes.c_int32, _P(ctypes.c_size_t)]
+_lib.rpm_fno_init.argtypes = [_P(FnoConfig), ctypes.c_uint64, _vp, _vp]
+_lib.rpm_fno_forward.argtypes = [_P(FnoConfig), _vp, _P(ctypes.c_int32), ctypes.c_int32, _vp, _vp, _vp,
+                                 ctypes.c_size_t, _vp]
+_lib.rpm_fno_backward.argtypes = [_P(FnoConfig), _vp, _P(ctypes.c_int32), ctypes.c_int32, _vp, _vp, _vp, _vp, _vp,
+                                  ctypes.c_size_t, _vp]
+_lib.rpm_fno_train_step.argtypes = [_P(FnoConfig), _vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_float,
+                                    _P(ctypes.c_int32), ctypes.c_int32, _vp, _vp, _dp, _vp, ctypes.c_size_t, _vp]
+_lib.rpm_fno_features.argtypes = [_P(RpmProblem), _vp, _vp]
+_lib.rpm_fno_warm_start.argtypes = [_P(FnoConfig), _vp, _P(RpmProblem), _dp, ctypes.c_int32, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
+for _f in EXPORTED_FNO:
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+def fno_config(c_in=2, c_out=36, width=32, layers=4, modes=12):
+    return FnoConfig(c_in, c_out, width, layers, modes)
+
+
+def _grid(shape):
+    nz, ny, nx = shape
+    return (ctypes.c_int32 * 3)(nx, ny, nz)
+
+
+def _f32(t, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float32 device tensor")
+    return t.data_ptr()
+
+
+def gemm_bf16(A, sA, B, sB, C, sC, M, N, K, batch=1, alpha=1.0, beta=0.0):
+    """rpm_gemm_bf16 on float32 device tensors with element strides (sA, sB, sC: 3 each)."""
+    rc = _lib.rpm_gemm_bf16(M, N, K, batch, _f32(A, "A"), (ctypes.c_int64 * 3)(*sA), _f32(B, "B"),
+                            (ctypes.c_int64 * 3)(*sB), _f32(C, "C"), (ctypes.c_int64 * 3)(*sC), alpha, beta, _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_gemm_bf16")
+    return C
+
+
+def fno_param_count(cfg):
+    c = ctypes.c_int64()
+    rc = _lib.rpm_fno_param_count(ctypes.byref(cfg), ctypes.byref(c))
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_param_count")
+    return c.value
+
+
+def fno_workspace(cfg, shape, batch, device="cuda"):
+    b = ctypes.c_size_t()
+    rc = _lib.rpm_fno_workspace_size(ctypes.byref(cfg), _grid(shape), batch, ctypes.byref(b))
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_workspace_size")
+    return torch.empty(b.value, dtype=torch.uint8, device=device)
+
+
+def fno_init(cfg, seed, device="cuda"):
+    p = torch.empty(fno_param_count(cfg), dtype=torch.float32, device=device)
+    rc = _lib.rpm_fno_init(ctypes.byref(cfg), seed, p.data_ptr(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_init")
+    return p
+
+
+def fno_forward(cfg, params, x, workspace=None):
+    """x: (batch, c_in, nz, ny, nx) float32 device tensor; returns y (batch, c_out, nz, ny, nx)."""
+    B, _, nz, ny, nx = x.shape
+    ws = workspace if workspace is not None else fno_workspace(cfg, (nz, ny, nx), B, x.device)
+    y = torch.empty((B, cfg.c_out, nz, ny, nx), dtype=torch.float32, device=x.device)
+    rc = _lib.rpm_fno_forward(ctypes.byref(cfg), _f32(params, "params"), _grid((nz, ny, nx)), B, _f32(x, "x"),
+                              y.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_forward")
+    return y, ws
+
+
+def fno_backward(cfg, params, x, dy, workspace, want_dx=False):
+    """Parameter gradient (and input gradient) of sum(dy * y) after fno_forward on workspace."""
+    B, _, nz, ny, nx = x.shape
+    g = torch.empty_like(params)
+    dx = torch.empty_like(x) if want_dx else None
+    rc = _lib.rpm_fno_backward(ctypes.byref(cfg), _f32(params, "params"), _grid((nz, ny, nx)), B, _f32(x, "x"),
+                               _f32(dy, "dy"), g.data_ptr(), dx.data_ptr() if dx is not None else None,
+                               workspace.data_ptr(), workspace.numel(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_backward")
+    return g, dx
+
+
+def fno_train_step(cfg, params, grad, m, v, step, lr, x, target, workspace):
+    B, _, nz, ny, nx = x.shape
+    loss = ctypes.c_double()
+    rc = _lib.rpm_fno_train_step(ctypes.byref(cfg), _f32(params, "params"), _f32(grad, "grad"), _f32(m, "m"),
+                                 _f32(v, "v"), step, lr, _grid((nz, ny, nx)), B, _f32(x, "x"),
+                                 _f32(target, "target"), ctypes.byref(loss), workspace.data_ptr(), workspace.numel(),
+                                 _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_train_step")
+    return loss.value
+
+
+def fno_features(phase, lame_tab):
+    pr = _problem(phase, lame_tab, (1.0, 1.0))
+    nz, ny, nx = phase.shape
+    x = torch.empty((2, nz, ny, nx), dtype=torch.float32, device=phase.device)
+    rc = _lib.rpm_fno_features(ctypes.byref(pr), x.data_ptr(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_features")
+    return x
+
+
+def fno_warm_start(cfg, params, phase, lame_tab, lame0, E, precision="fp64", workspace=None):
+    """Starting strain E + predicted fluctuation for rpm_fft_solve's eps0."""
+    pr = _problem(phase, lame_tab, lame0)
+    shape = tuple(phase.shape)
+    ws = workspace if workspace is not None else fno_workspace(cfg, shape, 1, phase.device)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    eps0 = torch.empty((6,) + shape, dtype=dt, device=phase.device)
+    Ea = (ctypes.c_double * 6)(*[float(e) for e in E])
+    rc = _lib.rpm_fno_warm_start(ctypes.byref(cfg), _f32(params, "params"), ctypes.byref(pr), Ea, PRECISION[precision],
+                                 eps0.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fno_warm_start")
+    return eps0

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "rpmfft.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("rpmfft.h", "rpmfno.h")]
 LIB = os.path.join(ROOT, "paper_2003_07720_amd", "librpmfft.so")
 
 
@@ -24,7 +24,7 @@ def B():
 
 
 def declared_functions():
-    txt = open(HEADER).read()
+    txt = "".join(open(h).read() for h in HEADERS)
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(rpm_[a-z_0-9]+)\s*\(", txt)))
 
@@ -35,7 +35,7 @@ def test_header_symbols_exported(B):
     assert len(names) >= 8
     for n in names:
         assert hasattr(lib, n), f"{n} declared in rpmfft.h but not exported"
-    assert sorted(B.EXPORTED) == names
+    assert sorted(B.EXPORTED + B.EXPORTED_FNO) == names
 
 
 def test_default_options_and_status_strings(B):
