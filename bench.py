@@ -133,6 +133,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--no-small", action="store_true", help="skip the 32^2 disk and 64^3 sphere rows")
+    ap.add_argument("--no-warm", action="store_true", help="skip training and timing the learned warm start")
+    ap.add_argument("--warm-cells", type=int, default=64, help="solver-generated training cells (32^3)")
+    ap.add_argument("--warm-steps", type=int, default=800, help="training steps of the warm-start network")
     ap.add_argument("--cpu-steps", type=int, default=14, help="oracle map applications in the CPU sample")
     ap.add_argument("--cpu-c2-maps", type=int, default=4,
                     help="single-threaded oracle map applications sampled on the 64^3 spheres")
@@ -150,7 +153,7 @@ def parse():
                          "(FP64 and FP32 refined), timed; prints its own JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of "
-                         "'bench.py --warmup 0 --no-cpu --no-ttt --no-small --calibrate-copy-mib M' into "
+                         "'bench.py --warmup 0 --no-cpu --no-ttt --no-small --no-warm --calibrate-copy-mib M' into "
                          "per-launch traffic (written to profiles/)")
     return ap.parse_args()
 
@@ -403,6 +406,7 @@ def main():
 
     # the small configurations on the GPU: the 32^2 disk (basic and RPM to 1e-8, FP64)
     small = {} if a.no_small else disk32_row(B, M, torch)
+    warm = None if a.no_warm else learned_warm_start(a, B, M, torch)
 
     cpu = None
     cpu_single = None
@@ -429,7 +433,8 @@ def main():
                                f"n_max 10, {prec_txt}; timed: {steps} steady-state steps at p = "
                                f"{r['basis_dim']} (basis carried from an untimed solve)",
                    "voxels": N, "p_timed": r["basis_dim"], "jvps_timed": r["jvps"],
-                   "time_to_tol_s": ttt, "time_to_tol_run": ttt_info, "small_configs": small},
+                   "time_to_tol_s": ttt, "time_to_tol_run": ttt_info, "learned_warm_start": warm,
+                   "small_configs": small},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "avg_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per_launch},
@@ -499,6 +504,39 @@ def time_to_tol(a, B, M, torch, phase, lt, l0, E, common, ws):
     info["basis_warm_start"] = bw
     print(f"bench: basis warm start {bw}", file=sys.stderr, flush=True)
     return ttt, info
+
+
+def learned_warm_start(a, B, M, torch):
+    """The learned warm start (NEXT-1): training data from the solver on seeded
+    32^3 cells (spheres, contrast 1e-3 .. 1e3), training with the library's
+    kernels, then the headline void cell solved from the uniform start and from
+    the network's prediction, to looser tolerances (1e-6 is out of reach for
+    both)."""
+    from paper_2003_07720_amd import surrogate as S
+
+    t0 = time.perf_counter()
+    X, Y, _ = S.make_dataset(32, a.warm_cells, 0)
+    Xv, Yv, _ = S.make_dataset(32, 8, 100000)
+    t1 = time.perf_counter()
+    cfg = B.fno_config(2, 36, 32, 4, 12)
+    params, hist = S.train(cfg, X, Y, steps=a.warm_steps, batch=4, lr=3e-3, seed=1, log_every=0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = dict(network="FNO: 2 features -> width 32, 4 spectral layers, 12 signed modes per axis -> 36 channels; "
+                       "BF16 matrix-core GEMMs, FP32 accumulation",
+               params=B.fno_param_count(cfg), train_cells=a.warm_cells, train_grid="32^3", steps=a.warm_steps,
+               data_seconds=round(t1 - t0, 1), train_seconds=round(t2 - t1, 1),
+               loss_first_last=[hist[0], float(np.mean(hist[-50:]))],
+               heldout_relative_error=round(S.relative_error(cfg, params, Xv, Yv), 4))
+    w = M.workload_voids128(seed=a.seed, n=a.n)
+    rows = {}
+    for tol in [float(x) for x in a.ttt_loose.split(",") if x] + [a.tol]:
+        rows[f"{tol:g}"] = S.compare_warm_start(cfg, params, w["phase"], w["phases"], w["E"], tol,
+                                                precision=a.precision, ref=(0.5 * (1 + 1e-8), 0.3),
+                                                max_iter=min(a.ttt_iters, 1000) if tol == a.tol else a.ttt_iters)
+    out["voids128"] = rows
+    print(f"bench: learned warm start {out}", file=sys.stderr, flush=True)
+    return out
 
 
 def disk32_row(B, M, torch):
