@@ -486,7 +486,8 @@ def time_to_tol(a, B, M, torch, phase, lt, l0, E, common, ws):
     Exx = np.zeros(6)
     Exx[0] = E[2]
     for tl in [float(x) for x in a.ttt_loose.split(",") if x]:
-        ob = B.make_options(max_iter=min(a.ttt_iters, 10 * (a.p_max // 2) + 12),
+        # about p_max / 2 columns: growth adds one or two every n_max + 1 steps
+        ob = B.make_options(max_iter=min(a.ttt_iters, 11 * (a.p_max // 4) + 1),
                             **dict(common, tol=tl, refine=0, p_max=a.p_max))
         torch.cuda.synchronize()
         b0 = time.perf_counter()

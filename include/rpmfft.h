@@ -114,9 +114,9 @@ typedef struct {
                                  p_max and map (else start from an empty basis;
                                  max_iter may differ).  The basis holds the
                                  linear part of that call's map: a call with
-                                 another reference medium, phase table or
-                                 alpha/beta also starts from an empty basis;
-                                 the phase map is not checked (keep it)         */
+                                 another reference medium, phase table,
+                                 alpha/beta or phase map (a checksum of it) also
+                                 starts from an empty basis                      */
     int32_t check_every;      /* host reads the convergence flag every this many
                                  iterations (>= 1); iterations queued after
                                  convergence do nothing                          */

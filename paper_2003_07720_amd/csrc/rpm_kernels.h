@@ -89,7 +89,8 @@ struct DevState {
     double best_err;   // lowest error below 0.9 x the previous lowest (stall test)
     int best_it;       // iteration at which best_err was reached
     int stall_window;  // stop (status 4) after this many iterations without a new best_err; 0 = off
-    double medium[6];  // lambda0, mu0, alpha, beta and a hash of the phase table the basis was built for
+    double medium[8];  // lambda0, mu0, alpha, beta, a hash of the phase table and a checksum of the phase map
+                       // the basis was built for
     double z[kMaxP], zeta[kMaxP], d[kMaxP];
     double zeta_ring[4][kMaxP];
     double H[kMaxP * kMaxP];
@@ -1394,6 +1395,30 @@ __global__ __launch_bounds__(kThreads) void k_step_end(DevState* __restrict__ st
         for (int j = 0; j < p; ++j) y += Ai[j * kMaxP + i] * r[j];
         st->d[i] = y - r[i];  // z' - zeta = (z + y) - zeta
     }
+}
+
+// Checksum of the phase map (part of the basis reuse key): per-block wrapping
+// sums of (phase + 1) * splitmix64(voxel index); integer sums, so the order
+// does not matter.
+__global__ __launch_bounds__(kThreads) void k_phase_sum(const uint8_t* __restrict__ phase, long long N,
+                                                        unsigned long long* __restrict__ part)
+{
+    __shared__ unsigned long long red[kThreads];
+    unsigned long long s = 0;
+    for (long long v = (long long)blockIdx.x * kThreads + threadIdx.x; v < N; v += (long long)gridDim.x * kThreads) {
+        unsigned long long z = (unsigned long long)v + 0x9e3779b97f4a7c15ull;
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+        z ^= z >> 31;
+        s += (unsigned long long)(phase[v] + 1) * z;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 // Clear the stop flags and the step counter (a fresh map evaluation).

@@ -669,8 +669,18 @@ rpm_status prepare(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, bool 
         }
     }
     const bool pol = o->map == RPM_MAP_POLARIZATION;
-    const double medium[6] = {c.lam0, c.mu0, pol ? o->alpha : 0.0, pol ? o->beta : 0.0,
-                              (double)(uint32_t)(h >> 32), (double)(uint32_t)h};
+    // and on the phase map: a device checksum (wrapping integer sums)
+    constexpr int kSumBlocks = 64;
+    unsigned long long* psum = reinterpret_cast<unsigned long long*>(c.pg());
+    k_phase_sum<<<kSumBlocks, kThreads, 0, c.s>>>(c.phase, g.N, psum);
+    unsigned long long parts[kSumBlocks];
+    if (hipMemcpyAsync(parts, psum, sizeof(parts), hipMemcpyDeviceToHost, c.s) != hipSuccess) return RPM_E_HIP;
+    if (hipStreamSynchronize(c.s) != hipSuccess) return RPM_E_HIP;
+    unsigned long long pk = 0;
+    for (int b = 0; b < kSumBlocks; ++b) pk += parts[b];
+    const double medium[8] = {c.lam0, c.mu0, pol ? o->alpha : 0.0, pol ? o->beta : 0.0,
+                              (double)(uint32_t)(h >> 32), (double)(uint32_t)h, (double)(uint32_t)(pk >> 32),
+                              (double)(uint32_t)pk};
     bool same = hs.magic == kStateMagic && std::memcmp(hs.cfg, cfg, sizeof(cfg)) == 0 &&
                 std::memcmp(hs.medium, medium, sizeof(medium)) == 0;
     if (!(same && want_reuse)) {

@@ -99,16 +99,19 @@ def test_basis_carried_between_solves_fp32(B):
     assert np.abs(eps - ref["eps"]).max() <= 1e-4 * np.abs(ref["eps"]).max()
 
 
-@pytest.mark.parametrize("change", ["medium", "table"])
+@pytest.mark.parametrize("change", ["medium", "table", "phase_map"])
 def test_reuse_with_another_map_starts_empty(B, change):
     """A reuse call whose map differs from the one the kept basis was built for
-    (another reference medium, or another phase table) starts from an empty
+    (another reference medium, another phase table, or another phase map of the
+    same grid) starts from an empty
     basis: it follows the solve in a fresh workspace step by step."""
     import torch
 
     print(f"reuse with another {change}", flush=True)
     ph, _ = M.rsa_spheres(16, 2.0, 3.0, 0.1, seed=9)
     gph = torch.from_numpy(ph).to("cuda")
+    ph_b = M.rsa_spheres(16, 2.0, 3.0, 0.1, seed=10)[0] if change == "phase_map" else ph
+    gph_b = torch.from_numpy(ph_b).to("cuda")
     lt_a = np.array([B.lame_from_young(*p) for p in PHASES])
     lt_b = np.array([B.lame_from_young(*p) for p in ([(1.0, 0.3), (15.0, 0.3)] if change == "table" else PHASES)])
     l0_a = B.lame_from_young(10.5, 0.3)
@@ -117,9 +120,9 @@ def test_reuse_with_another_map_starts_empty(B, change):
     ws = B.make_workspace(ph.shape, B.make_options(**common))
     ga = B.fft_solve(gph, lt_a, l0_a, EXX, B.make_options(**common), workspace=ws, want_eps=False)
     assert ga["status"] == "RPM_OK" and ga["basis_dim"] > 0
-    gb = B.fft_solve(gph, lt_b, l0_b, EZZ, B.make_options(reuse_basis=1, **common), workspace=ws)
+    gb = B.fft_solve(gph_b, lt_b, l0_b, EZZ, B.make_options(reuse_basis=1, **common), workspace=ws)
     ws2 = B.make_workspace(ph.shape, B.make_options(**common))
-    gf = B.fft_solve(gph, lt_b, l0_b, EZZ, B.make_options(**common), workspace=ws2)
+    gf = B.fft_solve(gph_b, lt_b, l0_b, EZZ, B.make_options(**common), workspace=ws2)
     assert gb["status"] == gf["status"] == "RPM_OK"
     assert gb["iterations"] == gf["iterations"] and gb["basis_dim"] == gf["basis_dim"]
     np.testing.assert_allclose(gb["history"], gf["history"], rtol=1e-12, atol=0)
