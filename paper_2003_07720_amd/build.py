@@ -32,6 +32,9 @@ def build(verbose=False):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
+    for obj in objs:  # intermediate objects do not travel with the tree
+        if os.path.exists(obj):
+            os.remove(obj)
     if r.returncode != 0:
         raise RuntimeError("hipcc link failed:\n" + r.stderr[-8000:])
     os.replace(OUT + ".tmp", OUT)
