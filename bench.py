@@ -35,7 +35,7 @@ KERNEL_SOURCES = ["include/rpmfft.h", "paper_2003_07720_amd/csrc/rpm_device.h",
                   "paper_2003_07720_amd/csrc/rpm_kernels.h", "paper_2003_07720_amd/csrc/rpm_solver.hip"]
 # kernel symbols behind each timing class of rpm_stats ({T}: float or double)
 CLASS_SYMBOLS = {
-    "xfwd": r"rpm::k_xfwd<{T}, (true|false), false(, \d+)?(, (true|false))?>",
+    "xfwd": r"rpm::k_xfwd<{T}, (true|false), false(, \d+)?(, (true|false)){0,2}>",
     "yfwd": r"rpm::k_ypipe<{T}, -1, \d+(, (true|false))?>|rpm::k_yfwd<{T}>",
     "gamma": r"rpm::k_(gamma|gpipe)<{T}, false(, (true|false))?>",
     "yinv": r"rpm::k_ypipe<{T}, 1, \d+(, (true|false))?>|rpm::k_yinv<{T}>",
@@ -381,7 +381,10 @@ def main():
     dom = max((k for k in kall if rk["kernel_launches"][k] > 0 and rk["kernel_bytes"][k] > 0), key=lambda k: kall[k])
     # 3. timed region: K steps, events only around the dominant class
     mask = 1 << B.KERNEL_NAMES.index(dom)
-    opts = B.make_options(max_iter=a.steps, profile=1, profile_classes=mask, **steady)
+    # events around about 30 of its launches, spread over the window (each event
+    # pair costs a few microseconds of the step it brackets)
+    every = max(1, a.steps // 30)
+    opts = B.make_options(max_iter=a.steps, profile=1, profile_classes=mask, profile_every=every, **steady)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = B.fft_solve(phase, lt, l0, E, opts, workspace=ws, want_eps=False)
@@ -437,7 +440,8 @@ def main():
                    "small_configs": small},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "avg_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per_launch},
+                     "avg_us": round(avg_ms * 1e3, 3), "bytes_per_launch": bytes_per_launch,
+                     "launches_timed": launches, "events_every": every},
         "kernels": per_kernel,
         "cpu_baseline": cpu,
         "cpu_single_thread": cpu_single,

@@ -161,6 +161,11 @@ typedef struct {
                                  recaptured when the basis grows; ignored with
                                  profile = 1 or a NULL stream, which cannot be
                                  captured); 0 = kernel by kernel                 */
+    int32_t profile_every;    /* with profile = 1: events around one launch in
+                                 every this many of each class (the first, then
+                                 every profile_every-th), so a long timed solve
+                                 carries few event records; 0 or 1 = every
+                                 launch (>= 0)                                   */
 } rpm_options;
 
 typedef struct {
@@ -188,7 +193,8 @@ typedef struct {
 /* Default options: tol 1e-6, max_iter 10000, n_max 10 (the near-optimal value
  * of Sec. 5.2), p_max 32, kappa 0.1, RPM, FP64, no reuse, check_every 16,
  * refine 4, refine_tol 1e-3, the Lippmann-Schwinger map, alpha = beta = 2,
- * no profiling (profile_classes 0), stall_window 400, batch_cases 0, graph 0. */
+ * no profiling (profile_classes 0, profile_every 1), stall_window 400,
+ * batch_cases 0, graph 0. */
 void rpm_default_options(rpm_options *o);
 
 /* Lame constants (lambda, mu) of an isotropic phase from Young's modulus E and

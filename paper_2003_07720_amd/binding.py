@@ -44,7 +44,8 @@ class RpmOptions(ctypes.Structure):
                 ("profile", ctypes.c_int32), ("refine", ctypes.c_int32), ("refine_tol", ctypes.c_double),
                 ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("profile_classes", ctypes.c_int32), ("stall_window", ctypes.c_int32),
-                ("batch_cases", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("batch_cases", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("profile_every", ctypes.c_int32)]
 
 
 class RpmStats(ctypes.Structure):

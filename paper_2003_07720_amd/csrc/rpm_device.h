@@ -181,11 +181,12 @@ __device__ __forceinline__ void dftR(cx<T>* v)
 }
 
 // LDS layout of the pencils: element i of a sequence sits at lpad(i) (one
-// spare slot after every 32 elements) and sequences are lrow(n) slots apart.
-// The spare slots break the power-of-two strides of the Stockham writes and
-// of column-wise fills, which otherwise land on a few LDS banks.
-__host__ __device__ constexpr int lpad(int i) { return i + (i >> 5); }
-__host__ __device__ constexpr int lrow(int n) { return n + (n >> 5) + 1; }
+// spare slot after every 16 elements) and sequences are lrow(n) slots apart.
+// The spare slots break the power-of-two strides of the Stockham writes
+// (16 j + q in the first radix-16 stage) and of column-wise fills (runs of
+// four voxels per lane), which otherwise land on a few LDS banks.
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lrow(int n) { return n + (n >> 4) + 1; }
 
 // One Stockham stage over nseq sequences of length n held in LDS with row
 // stride ss.  Ns = product of the radices already applied.

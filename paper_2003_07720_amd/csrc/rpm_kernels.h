@@ -42,6 +42,12 @@ __device__ __forceinline__ double2 nt_load(const double2* p)
 #ifndef RPM_GIP_WPE
 #define RPM_GIP_WPE 5
 #endif
+#ifndef RPM_RC_GROUP
+#define RPM_RC_GROUP 8
+#endif
+#ifndef RPM_RC_WPE
+#define RPM_RC_WPE 4
+#endif
 
 struct Geo {
     int nx, ny, nz, nh;    // nh = nx/2 + 1 (half spectrum along x)
@@ -128,15 +134,23 @@ struct MaxV<double> { static constexpr int v = 4; };
 // x-forward: constitutive law + R2C FFT along x (two real components per
 // complex transform), per-block <eps> partial sums.  POL: eps is transformed
 // too (components 6..11 of S1), for the polarization iteration.
+// RC (RPM iterations, VEC only): the strain is recombined on the way in,
+// eps = xin + sum_{j < p} d_j Z_j, in the order and rounding of k_recombine,
+// and stored to eps_out (the x-inverse pass reads it); the tile's basis
+// slices stream through eight columns at a time.
 // grid: nz * (ny / ty) blocks.  LDS: 2 * ty * lrow(nx) + nx complex + reduction.
 // ---------------------------------------------------------------------------
-template <typename T, bool VEC, bool POL, int NT, bool IP>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_xfwd(const T* __restrict__ xin, const uint8_t* __restrict__ phase,
+template <typename T, bool VEC, bool POL, int NT, bool IP, bool RC = false>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? (RC ? RPM_RC_WPE : 4) : 2))) void k_xfwd(const T* __restrict__ xin, const uint8_t* __restrict__ phase,
                                                    const double* __restrict__ lame, int use_ref, double lam0,
                                                    double mu0, cx<T>* __restrict__ S1,
                                                    double* __restrict__ part_mean, Geo g, Plan px,
-                                                   const cx<T>* __restrict__ twx, const int* __restrict__ done)
+                                                   const cx<T>* __restrict__ twx, const int* __restrict__ done,
+                                                   const T* __restrict__ Z = nullptr, int p = 0, int zP = 0,
+                                                   const double* __restrict__ dco = nullptr,
+                                                   T* __restrict__ eps_out = nullptr)
 {
+    static_assert(!RC || VEC, "recombination on the way in needs 16-byte runs");
     if (done && *done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int MV = MaxV<T>::v * kThreads / NT;  // voxels per thread
@@ -145,6 +159,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     cx<T>* B = A + ty * ss;
     cx<T>* tw = IP ? B : B + ty * ss;  // IP: one buffer, transforms in place
     double* red = reinterpret_cast<double*>(tw + nx);
+    constexpr int RG = RPM_RC_GROUP;  // basis columns in flight per thread
+    __shared__ T dj[RC ? kMaxP + RG : 1];
+    if constexpr (RC) {
+        for (int j = threadIdx.x; j < kMaxP + RG; j += NT) dj[j] = j < p ? (T)dco[j] : T(0);
+        __syncthreads();
+    }
 
     const int nyt = g.ny / ty;
     const int z = blockIdx.x / nyt;
@@ -170,7 +190,29 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
             const int v0 = (threadIdx.x + i * NT) * VL;
             const long long gi = base + v0;
             if (v0 < nvox) {
-                if constexpr (VEC) {
+                if constexpr (RC) {
+                    // a wave's run covers contiguous elements of one basis tile per column
+                    const long long el = c * N + gi;
+                    V acc = *reinterpret_cast<const V*>(xin + el);
+                    T* a = reinterpret_cast<T*>(&acc);
+                    const T* zt = Z + zix(el, 0, zP);
+                    for (int gq = 0; gq < p; gq += RG) {
+                        V zv[RG];
+#pragma unroll
+                        for (int u = 0; u < RG; ++u)
+                            zv[u] = nt_load(reinterpret_cast<const V*>(zt + (long long)min(gq + u, p - 1) * kZTile));
+#pragma unroll
+                        for (int u = 0; u < RG; ++u) {
+                            const T* zs = reinterpret_cast<const T*>(&zv[u]);
+                            const T cf = dj[gq + u];
+#pragma unroll
+                            for (int q = 0; q < VL; ++q) a[q] += cf * zs[q];
+                        }
+                    }
+                    *reinterpret_cast<V*>(eps_out + el) = acc;
+#pragma unroll
+                    for (int u = 0; u < VL; ++u) e[i * VL + u][c] = a[u];
+                } else if constexpr (VEC) {
                     const V t = *reinterpret_cast<const V*>(xin + c * N + gi);
                     const T* ts = reinterpret_cast<const T*>(&t);
 #pragma unroll
@@ -1315,9 +1357,26 @@ __global__ __launch_bounds__(kThreads) void k_step_end(DevState* __restrict__ st
     __shared__ double dprev[kMaxP], r[kMaxP];
     __shared__ double Gs[kMaxP * kMaxP], Ai[kMaxP * kMaxP];
     const int t = threadIdx.x;
+    // thread 0 reads every state scalar of the step at once (independent
+    // loads, one memory round trip) before any decision
+    int done0 = 0, sing0 = 0, it0 = 0, maxit = 0, win = 0, bit = 0;
+    double err00 = 0.0, tol = 0.0, gnorm = 1.0, best = 0.0, num = 0.0, s[6] = {0, 0, 0, 0, 0, 0};
     if (t == 0) {
-        sdone = st->done;
-        ssing = st->singular;
+        done0 = st->done;
+        sing0 = st->singular;
+        it0 = st->iters;
+        maxit = st->max_iter;
+        win = st->stall_window;
+        bit = st->best_it;
+        err00 = st->err0;
+        tol = st->tol;
+        gnorm = st->gnorm;
+        best = st->best_err;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] = st->sig_hat0[c];
+        num = sums[0];
+        sdone = done0;
+        ssing = sing0;
     }
     __syncthreads();
     if (sdone) return;  // uniform
@@ -1328,53 +1387,59 @@ __global__ __launch_bounds__(kThreads) void k_step_end(DevState* __restrict__ st
         Ai[i * kMaxP + j] = st->AinvT[i * kMaxP + j];
     }
     for (int j = t; j < p; j += kThreads) dprev[j] = st->d[j];
+    // this thread's basis coordinate (t < p): loads issued with the others
+    double ze = 0.0, zz = 0.0;
+    if (t < p) {
+        ze = sums[1 + t];
+        zz = direct ? sums[1 + p + t] : st->zeta[t];
+    }
     if (t == 0) {
+        int done = 0;
         if (!newton_only) {
-            const double* s = st->sig_hat0;
             const double den = two_d ? (s[0] * s[0] + s[1] * s[1] + 2.0 * s[5] * s[5])
                                      : (s[0] * s[0] + s[1] * s[1] + s[2] * s[2] +
                                         2.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
-            const double num = sums[0] > 0.0 ? sums[0] : 0.0;
+            const double nm = num > 0.0 ? num : 0.0;
             // err_mode 0: equilibrium error of the iterate; 1: fixed-point increment
             // |G(d) - d| / |g| of a correction solve
-            const double err = err_mode == 0 ? sqrt(num) / sqrt(den) : sqrt(num) / st->gnorm;
-            const int it = ++st->iters;
+            const double err = err_mode == 0 ? sqrt(nm) / sqrt(den) : sqrt(nm) / gnorm;
+            const int it = it0 + 1;
+            st->iters = it;
             if (hist && it - 1 < hist_cap) hist[it - 1] = err;
-            if (it == 1) st->err0 = err;
+            if (it == 1) {
+                st->err0 = err;
+                err00 = err;
+            }
             st->err = err;
-            if (!(err == err) || isinf(err) || err > 1e6 * st->err0) {
-                st->status = 2;
-                st->done = 1;
-            } else if (err <= st->tol) {
-                st->status = 0;
-                st->done = 1;
-            } else if (it >= st->max_iter) {
-                st->status = 1;
-                st->done = 1;
-            } else if (st->stall_window > 0) {
+            int status = -1;
+            if (!(err == err) || isinf(err) || err > 1e6 * err00) {
+                status = 2;
+            } else if (err <= tol) {
+                status = 0;
+            } else if (it >= maxit) {
+                status = 1;
+            } else if (win > 0) {
                 // stalled: no error below 0.9 x the lowest one for stall_window iterations
-                if (err < 0.9 * st->best_err) {
+                if (err < 0.9 * best) {
                     st->best_err = err;
                     st->best_it = it;
-                } else if (it - st->best_it >= st->stall_window) {
-                    st->status = 4;
-                    st->done = 1;
+                } else if (it - bit >= win) {
+                    status = 4;
                 }
             }
+            if (status >= 0) {
+                st->status = status;
+                st->done = 1;
+                done = 1;
+            }
         }
-        snow = st->done;
+        snow = done;
     }
     __syncthreads();
     if (t < p) {
         const int i = t;
-        const double ze = sums[1 + i];
-        double zz;
-        if (direct) {
-            zz = sums[1 + p + i];
-        } else {
-            zz = st->zeta[i];
+        if (!direct)
             for (int j = 0; j < p; ++j) zz += Gs[j * kMaxP + i] * dprev[j];
-        }
         st->zeta[i] = ze;
         st->z[i] = zz;
         st->zeta_ring[slot][i] = ze;

@@ -68,6 +68,12 @@ constexpr bool kGInPlace = RPM_G_INPLACE != 0;  // in-place gamma transforms
 #define RPM_X_INPLACE 1
 #endif
 constexpr bool kXInPlace = RPM_X_INPLACE != 0;  // in-place x transforms
+#ifndef RPM_FUSE_RECOMBINE
+#define RPM_FUSE_RECOMBINE 1
+#endif
+// RPM recombination inside the x-forward pass (in-place 128-point x
+// transforms, not the polarization map)
+constexpr bool kFuseRecombine = RPM_FUSE_RECOMBINE != 0;
 constexpr int kGipBlocks = RPM_GIP_BLOCKS;      // persistent grid with in-place transforms
 constexpr int kGPipeBlocks = RPM_GPIPE_BLOCKS;  // its persistent grid
 #ifndef RPM_X_NT
@@ -345,6 +351,8 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o, bool map_only)
 struct Prof {
     bool on = false;
     uint32_t mask = ~0u;  // kernel classes recorded
+    int every = 1;        // one launch in every this many of a class
+    int seen[RPM_NKERNEL] = {0};
     std::vector<hipEvent_t> pool;
     struct Rec {
         hipEvent_t a, b;
@@ -387,6 +395,7 @@ struct Prof {
             ms[k] = 0.0;
             n[k] = 0;
             bytes[k] = 0.0;
+            seen[k] = 0;
         }
     }
     ~Prof()
@@ -438,6 +447,7 @@ struct Ctx {
     {
         a = nullptr;
         if (!prof.on || !((prof.mask >> k) & 1u)) return;
+        if (prof.seen[k]++ % prof.every != 0) return;
         a = prof.get();
         if (a) hipEventRecord(a, s);
     }
@@ -473,7 +483,21 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     const double specB = 6.0 * (double)g.nspec * sizeof(cx<T>);
     const double bi = specB + fieldB * (2 + (shift ? 1 : 0));
     hipEvent_t ev;
-    if (eps_store) {
+    const bool pol = c.pol && out_mode == OUT_XI;
+    const bool vec = g.nx % (16 / (int)sizeof(T)) == 0;
+    constexpr int XT = x_threads<T>();
+    const double cf = (double)g.ncomp / 6.0;  // spectral components carried forward, over 6
+    const double bx = fieldB + (use_ref ? 0.0 : (double)g.N) + cf * specB;
+    const bool fuse = eps_store && kFuseRecombine && sh.xip && vec && !pol;
+    if (fuse) {
+        // eps = xin + Z d recombined inside the x pass (stored for the x-inverse)
+        c.mark_begin(RPM_K_XFWD, ev);
+        k_xfwd<T, true, false, XT, true, true><<<sh.G1, XT, sh.lds_x, c.s>>>(
+            xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, g, sh.px, c.twx(), done, c.Zb(), p_corr,
+            c.pmax, c.st->d, eps_store);
+        c.mark_end(RPM_K_XFWD, ev, bx + fieldB * (1 + p_corr));
+    }
+    if (eps_store && !fuse) {
         // eps = xin + Z d (a copy while p = 0) as its own streaming pass; the x
         // pass then reads eps
         const long long nel = 6 * g.N;
@@ -484,16 +508,12 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         c.mark_end(RPM_K_RECOMBINE, ev, fieldB * (2 + p_corr));
         xin = eps_store;
     }
-    const double cf = (double)g.ncomp / 6.0;  // spectral components carried forward, over 6
-    const double bx = fieldB + (use_ref ? 0.0 : (double)g.N) + cf * specB;
-    const bool pol = c.pol && out_mode == OUT_XI;
-    c.mark_begin(RPM_K_XFWD, ev);
-    const bool vec = g.nx % (16 / (int)sizeof(T)) == 0;
-    constexpr int XT = x_threads<T>();
+    if (!fuse) c.mark_begin(RPM_K_XFWD, ev);
 #define RPM_XFWD(V, P, I)                                                                                      \
     k_xfwd<T, V, P, XT, I><<<sh.G1, XT, sh.lds_x, c.s>>>(xin, c.phase, c.lame(), use_ref, c.lam0, c.mu0, S1, pmean, \
                                                          g, sh.px, c.twx(), done)
-    if (sh.xip) {
+    if (fuse) {
+    } else if (sh.xip) {
         if (pol) {
             if (vec) RPM_XFWD(true, true, true);
             else RPM_XFWD(false, true, true);
@@ -511,7 +531,7 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         }
     }
 #undef RPM_XFWD
-    c.mark_end(RPM_K_XFWD, ev, bx);
+    if (!fuse) c.mark_end(RPM_K_XFWD, ev, bx);
     if (!g.two_d) {
         const int tiles = pol ? sh.Gyf : sh.Gy;
         c.mark_begin(RPM_K_YFWD, ev);
@@ -1311,6 +1331,7 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->stall_window < 0) return RPM_E_INVALID;
     if (o->batch_cases < 0 || o->batch_cases > 2) return RPM_E_INVALID;
     if (o->graph != 0 && o->graph != 1) return RPM_E_INVALID;
+    if (o->profile_every < 0) return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
         return RPM_E_INVALID;
@@ -1342,6 +1363,7 @@ rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void
     c.beta = o->beta;
     c.prof.on = o->profile != 0;
     c.prof.mask = o->profile_classes ? (uint32_t)o->profile_classes : ~0u;
+    c.prof.every = o->profile_every > 1 ? o->profile_every : 1;
     return RPM_OK;
 }
 
@@ -1865,6 +1887,7 @@ void rpm_default_options(rpm_options* o)
     o->stall_window = 400;
     o->batch_cases = 0;
     o->graph = 0;
+    o->profile_every = 1;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)

@@ -1,6 +1,7 @@
 """Writes ceff_32cube.json: effective stiffness tensors of two 32^3 cells computed
 by the FP64 CPU oracle (Algorithm 2, every unit load case, error tolerance
-1e-8), the expected values of the FP32-refined effective-tensor parity tests.
+1e-7: the effective tensor is stationary at the solution, so its error is far
+below 1e-7), the expected values of the FP32-refined effective-tensor parity tests.
 Calls only the oracle and the seeded input generators.
 
   python tests/golden/make_ceff_32cube.py
@@ -26,7 +27,7 @@ CELLS = {
     "voids32_contrast1e-3": (dict(n=32, r_min=1.5, r_max=3.0, vf=0.30, seed=3000), [(1.0, 0.3), (1e-3, 0.3)],
                              (1.0, 0.3)),
 }
-TOL = 1e-8
+TOL = 1e-7
 
 
 def cell_phase(gen):
@@ -34,9 +35,15 @@ def cell_phase(gen):
     return ph, info
 
 
-def main():
+def main(names=None):
     out = {"tol": TOL, "scheme": "rpm", "n_max": 10, "p_max": 32, "cells": {}}
+    path = os.path.join(HERE, "ceff_32cube.json")
+    if os.path.exists(path):
+        with open(path) as fh:
+            out["cells"] = json.load(fh).get("cells", {})
     for name, (gen, phases, ref) in CELLS.items():
+        if names and name not in names:
+            continue
         ph, info = cell_phase(gen)
         t0 = time.time()
         C, runs = O.effective_tensor(ph, O.lame_table(phases), O.lame(*ref), scheme="rpm", tol=TOL,
@@ -45,9 +52,15 @@ def main():
         out["cells"][name] = dict(generator=gen, phases=phases, ref=ref, vf=float(info["vf"]), C_eff=C.tolist(),
                                   iterations=[r["iterations"] for r in runs], seconds=round(time.time() - t0, 1))
         print(name, out["cells"][name]["iterations"], out["cells"][name]["seconds"], flush=True)
-    with open(os.path.join(HERE, "ceff_32cube.json"), "w") as fh:
-        json.dump(out, fh, indent=1)
+        # merge with what another run wrote meanwhile
+        if os.path.exists(path):
+            with open(path) as fh:
+                cells = json.load(fh).get("cells", {})
+            cells[name] = out["cells"][name]
+            out["cells"] = cells
+        with open(path, "w") as fh:
+            json.dump(out, fh, indent=1)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])

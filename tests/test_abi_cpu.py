@@ -43,7 +43,7 @@ def test_default_options_and_status_strings(B):
     assert o.tol == 1e-6 and o.max_iter == 10000 and o.n_max == 10 and o.p_max == 32
     assert abs(o.kappa - 0.1) < 1e-15 and o.scheme == 1 and o.precision == 0 and o.check_every == 16
     assert o.map == 0 and o.alpha == 2.0 and o.beta == 2.0
-    assert o.profile == 0 and o.profile_classes == 0
+    assert o.profile == 0 and o.profile_classes == 0 and o.profile_every == 1
     for code, name in B.STATUS.items():
         assert B.status_string(code) == name
     assert B.status_string(99) == "RPM_UNKNOWN"
@@ -101,7 +101,7 @@ def _raw_problem(B, n=(8, 8, 8), lame=((1.0, 1.0),), lame0=(1.0, 1.0)):
 
 
 @pytest.mark.parametrize("case", ["tol", "nan_E", "pmax", "mu0", "neg_mu", "scheme", "check", "size", "nphase",
-                                  "workspace", "kappa", "replay", "map", "alpha", "classes"])
+                                  "workspace", "kappa", "replay", "map", "alpha", "classes", "every"])
 def test_solve_rejects_bad_arguments_before_device_work(B, case):
     lib = B._lib
     o = B.make_options()
@@ -143,6 +143,9 @@ def test_solve_rejects_bad_arguments_before_device_work(B, case):
     elif case == "classes":
         o.profile = 1
         o.profile_classes = 1 << B.RPM_NKERNEL
+    elif case == "every":
+        o.profile = 1
+        o.profile_every = -2
     rc = lib.rpm_fft_solve(ctypes.byref(pr), E, ctypes.byref(o), None, None, None, None, None, ws, wsb, None)
     assert rc == expect, (case, rc)
     rc = lib.rpm_fft_effective_tensor(ctypes.byref(pr), ctypes.byref(o), (ctypes.c_double * 36)(), None, ws, wsb,

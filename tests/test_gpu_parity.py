@@ -104,7 +104,8 @@ def test_rpm_disk32_fp64(B, n_max):
     assert list(g2["decisions"]) == list(ref["decisions"])
 
 
-@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 12, 16)], ids=lambda s: "x".join(map(str, s)))
+# (6, 12, 128): 128-point x transforms in place, with the recombination inside the x pass
+@pytest.mark.parametrize("shape", [(8, 8, 8), (6, 12, 16), (6, 12, 128)], ids=lambda s: "x".join(map(str, s)))
 def test_rpm_random_3d_fp64(B, shape):
     ph = M.random_phases(shape, 2, seed=101)
     phases = [(1.0, 0.3), (100.0, 0.3)]
@@ -117,6 +118,23 @@ def test_rpm_random_3d_fp64(B, shape):
     assert g["iterations"] == ref["iterations"] and g["basis_dim"] == ref["p"]
     eps = g["eps"].cpu().numpy()
     assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
+
+
+def test_rpm_random_3d_fp32_fused_x_pass(B):
+    """FP32 fields on a grid whose x pass recombines eps = xi + Z d on the way
+    in (nx = 128): the certified solution matches the oracle's (FP32 bar: 1e-4
+    relative in the field)."""
+    ph = M.random_phases((6, 12, 128), 2, seed=102)
+    phases = [(1.0, 0.3), (100.0, 0.3)]
+    E = np.array([0.0, 0.0, 0.01, 0.0, 0.003, 0.0])
+    l0 = O.lame(50.5, 0.3)
+    ref = O.solve(ph, O.lame_table(phases), l0, E, scheme="rpm", tol=1e-10, n_max=6, p_max=16, max_iter=3000)
+    g = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(50.5, 0.3), E,
+                    B.make_options(scheme="rpm", precision="fp32", tol=1e-7, n_max=6, p_max=16, max_iter=3000))
+    assert ref["status"] == "converged" and g["status"] == "RPM_OK" and g["basis_dim"] > 0
+    assert g["residual_fp64"] <= 1e-7
+    eps = g["eps"].cpu().numpy().astype(np.float64)
+    assert np.abs(eps - ref["eps"]).max() <= 1e-4 * np.abs(ref["eps"]).max()
 
 
 def test_warm_start_parity_fp64(B):
