@@ -551,7 +551,7 @@ def disk32_row(B, M, torch):
     and from graphs), one load case of the 64^3 spheres (E0 at the stiff
     modulus, RPM to 1e-6, FP64 and FP32 refined, basis cap 32 and 64) and their
     6 x 6 effective tensor (load cases one after the other, and batched on one
-    shared basis)."""
+    shared basis), and the tile autotuner on 48^3 and 96^3 cells."""
     out = {}
     side = torch.cuda.Stream()
 
@@ -598,6 +598,29 @@ def disk32_row(B, M, torch):
             out[f"spheres64_ceff_fp64_p{p_max}" + ("_batched" if batch else "")] = dict(
                 status=st, seconds=round(el, 4), iterations=[x["iterations"] for x in stats],
                 jvps=sum(x["jvps"] for x in stats), C11=C[0][0], C33=C[2][2])
+        # the uneven grids of the batched benchmark family: the tile autotuner's
+        # shape against the default, per map application (FP32)
+        for n in (48, 96):
+            cell = M.random_phases((n, n, n), 2, seed=40 + n)
+            ph = torch.from_numpy(cell).to("cuda")
+            lt = np.array([B.lame_from_young(*p) for p in [(1.0, 0.3), (50.0, 0.3)]])
+            l0 = B.lame_from_young(50.0, 0.3)
+            o = B.make_options(scheme="rpm", precision="fp32", p_max=32)
+            ws = B.make_workspace(tuple(ph.shape), o)
+            t0 = time.perf_counter()
+            t = B.autotune(ph, lt, l0, o, reps=20, workspace=ws)
+            tune_s = time.perf_counter() - t0
+            ms = {}
+            for name, tn in (("default", None), ("tuned", t["tuning"])):
+                # 200 RPM steps each (a tolerance no step reaches), basis up to 32
+                oo = B.make_options(scheme="rpm", precision="fp32", p_max=32, tol=1e-15, max_iter=200, refine=0,
+                                    check_every=32, tuning=tn)
+                r, el = timed(lambda: B.fft_solve(ph, lt, l0, Ezz, oo, workspace=ws, want_eps=False))
+                ms[name] = round(el / (r["iterations"] + r["jvps"]) * 1e3, 4)
+            out[f"autotune_{n}cube_fp32"] = dict(tuning=t["tuning"].as_dict(), tuner_ms_per_map=round(t["ms"], 4),
+                                                 candidates=t["candidates"], tune_seconds=round(tune_s, 3),
+                                                 ms_per_map_solve_default=ms["default"],
+                                                 ms_per_map_solve_tuned=ms["tuned"])
     print(f"bench: small configurations {out}", file=sys.stderr, flush=True)
     return out
 

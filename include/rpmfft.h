@@ -58,6 +58,23 @@
 extern "C" {
 #endif
 
+/* Launch shape of the y and gamma pencil passes of one grid and precision
+ * (the batched, uneven-grid workloads of the paper's benchmark families run
+ * many grids; the best shape differs between them).  A field of 0 keeps the
+ * library's default.  None changes a result: every element is transformed
+ * with the same arithmetic; only the grouping of the per-block error partial
+ * sums follows gamma_blocks.
+ *   y_cols        z positions per y-pass tile: a divisor of nz, at most
+ *                 128 / (2 sizeof(real)) and 8 x 256 / ny; other values make
+ *                 the calls that use the tuning return RPM_E_INVALID
+ *   y_blocks      workgroups of the persistent y passes (>= 1)
+ *   gamma_blocks  workgroups of the persistent gamma pass (>= 1)          */
+typedef struct rpm_tuning_s {
+    int32_t y_cols;
+    int32_t y_blocks;
+    int32_t gamma_blocks;
+} rpm_tuning;
+
 typedef enum {
     RPM_OK = 0,                 /* error <= tol                                  */
     RPM_NOT_CONVERGED = 1,      /* max_iter main-loop F applications reached     */
@@ -166,6 +183,10 @@ typedef struct {
                                  every profile_every-th), so a long timed solve
                                  carries few event records; 0 or 1 = every
                                  launch (>= 0)                                   */
+    const struct rpm_tuning_s *tuning; /* HOST, nullable: launch shape of the
+                                 pencil passes (rpm_fft_autotune); NULL = the
+                                 library's defaults.  The workspace size does
+                                 not depend on it.                               */
 } rpm_options;
 
 typedef struct {
@@ -211,13 +232,35 @@ rpm_status rpm_lame_from_young(double E, double nu, double *lam, double *mu);
 rpm_status rpm_workspace_size(const int32_t n[3], const rpm_options *o, size_t *bytes);
 
 /*
- * One application of the fixed-point map (Algorithm 1, lines 5-9):
+ * One application of the fixed-point map (the iteration body of Algorithm 1):
  * xi = F(eps; E) and the equilibrium error of eps, <sigma> = <C(x):eps>.
  * eps, xi: DEVICE fields in o->precision (may not alias).  err, sig_avg: HOST
  * (nullable).
  */
 rpm_status rpm_fft_apply(const rpm_problem *pr, const double E[6], const rpm_options *o, const void *eps, void *xi,
                          double *err, double sig_avg[6], void *workspace, size_t ws_bytes, void *hip_stream);
+
+/*
+ * Tile autotuner of the pencil passes: times the fixed-point map of the
+ * iteration body of Algorithm 1 (from the uniform strain, on the workspace's
+ * own fields) under candidate launch shapes and returns the fastest.  One
+ * coordinate at a time, in this order, each from the best so far: y_cols over
+ * the admissible divisors of nz (largest first, at most four), then y_blocks
+ * and gamma_blocks over 256 x {1, 2, 3, 4, 5, 6, 8} capped at the number of
+ * tiles; 0 is tried first for each (the default).  Each candidate: one
+ * untimed map, then reps maps between HIP events.
+ *   reps      1 .. 1000
+ *   best      HOST: the fastest shape (fields of 0 where the default won)
+ *   best_ms   HOST nullable: its time per map application
+ *   candidates HOST nullable: number of shapes timed
+ * o->tuning is ignored.  The workspace holds rpm_workspace_size(n, o) bytes;
+ * its fields and basis are overwritten (the stored basis is kept only if the
+ * same workspace is not tuned: call this before the solves that reuse it).
+ * Errors as rpm_fft_apply; RPM_E_INVALID for reps out of range or NULL best.
+ */
+rpm_status rpm_fft_autotune(const rpm_problem *pr, const rpm_options *o, int32_t reps, rpm_tuning *best,
+                            double *best_ms, int32_t *candidates, void *workspace, size_t ws_bytes,
+                            void *hip_stream);
 
 /*
  * Solve the cell problem for the mean strain E (Sec. 2) with Algorithm 1 or

@@ -7,8 +7,8 @@ arithmetic lives in ``oracle.c`` (plain C, FP64, compiled with
 
 Each wrapper names the passage of the paper it follows:
 
-* :func:`fmap` -- the Lippmann-Schwinger fixed-point map of Algorithm 1
-  (lines 5-9) and the operator F defined in Sec. 3, in the literal form that
+* :func:`fmap` -- the Lippmann-Schwinger fixed-point map (the iteration body
+  of Algorithm 1) and the operator F defined in Sec. 3, in the literal form that
   transforms both strain and stress;
 * :func:`solve` -- Algorithm 1 (``scheme="basic"``) or Algorithm 2
   (``scheme="rpm"``) for one mean strain E (Sec. 2: the average strain is

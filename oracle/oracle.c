@@ -266,7 +266,7 @@ void orc_stress(long N, const unsigned char *phase, const double *lame, const do
 }
 
 /* ------------------------------------------------------------------------ */
-/* The Lippmann-Schwinger map F (Algorithm 1, lines 5-9; Sec. 3 definition) */
+/* The Lippmann-Schwinger map F (the iteration body of Algorithm 1; Sec. 3)   */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {

@@ -36,6 +36,13 @@ class RpmProblem(ctypes.Structure):
                 ("lame", ctypes.POINTER(ctypes.c_double)), ("lame0", ctypes.c_double * 2)]
 
 
+class RpmTuning(ctypes.Structure):
+    _fields_ = [("y_cols", ctypes.c_int32), ("y_blocks", ctypes.c_int32), ("gamma_blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(y_cols=self.y_cols, y_blocks=self.y_blocks, gamma_blocks=self.gamma_blocks)
+
+
 class RpmOptions(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("n_max", ctypes.c_int32),
                 ("p_max", ctypes.c_int32), ("kappa", ctypes.c_double), ("scheme", ctypes.c_int32),
@@ -45,7 +52,7 @@ class RpmOptions(ctypes.Structure):
                 ("map", ctypes.c_int32), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
                 ("profile_classes", ctypes.c_int32), ("stall_window", ctypes.c_int32),
                 ("batch_cases", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("profile_every", ctypes.c_int32)]
+                ("profile_every", ctypes.c_int32), ("tuning", ctypes.POINTER(RpmTuning))]
 
 
 class RpmStats(ctypes.Structure):
@@ -77,10 +84,13 @@ _lib.rpm_fft_solve_stress.argtypes = [_P(RpmProblem), _dp, _P(RpmOptions), _vp, 
 _lib.rpm_fft_seed_basis.argtypes = [_P(RpmProblem), _P(RpmOptions), _vp, ctypes.c_int32, _P(ctypes.c_int32), _vp,
                                     ctypes.c_size_t, _vp]
 _lib.rpm_workspace_h.argtypes = [_vp, ctypes.c_size_t, _dp, ctypes.c_int32, _P(ctypes.c_int32), _vp]
+_lib.rpm_fft_autotune.argtypes = [_P(RpmProblem), _P(RpmOptions), ctypes.c_int32, _P(RpmTuning), _dp,
+                                  _P(ctypes.c_int32), _vp, ctypes.c_size_t, _vp]
 _lib.rpm_status_string.argtypes = [ctypes.c_int]
 _lib.rpm_status_string.restype = ctypes.c_char_p
 for _f in ("rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply", "rpm_fft_apply_static", "rpm_fft_solve", "rpm_fft_effective_tensor",
-           "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress", "rpm_workspace_h"):
+           "rpm_workspace_basis_dim", "rpm_fft_seed_basis", "rpm_fft_solve_stress", "rpm_workspace_h",
+           "rpm_fft_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED_FNO = ["rpm_gemm_bf16", "rpm_fno_param_count", "rpm_fno_workspace_size", "rpm_fno_init", "rpm_fno_forward",
@@ -89,7 +99,7 @@ EXPORTED_FNO = ["rpm_gemm_bf16", "rpm_fno_param_count", "rpm_fno_workspace_size"
 EXPORTED = ["rpm_default_options", "rpm_lame_from_young", "rpm_workspace_size", "rpm_fft_apply",
             "rpm_fft_apply_static", "rpm_fft_solve",
             "rpm_fft_effective_tensor", "rpm_fft_solve_stress", "rpm_fft_seed_basis", "rpm_workspace_basis_dim",
-            "rpm_workspace_h", "rpm_status_string"]
+            "rpm_workspace_h", "rpm_status_string", "rpm_fft_autotune"]
 
 
 class RpmError(RuntimeError):
@@ -115,6 +125,7 @@ def make_options(**kw):
     o = RpmOptions()
     _lib.rpm_default_options(ctypes.byref(o))
     replay = kw.pop("replay", None)
+    tuning = kw.pop("tuning", None)
     for k, v in kw.items():
         if k == "scheme" and isinstance(v, str):
             v = SCHEME[v]
@@ -129,6 +140,10 @@ def make_options(**kw):
         o.replay = ctypes.cast(keep, _P(ctypes.c_int32))
         o.replay_len = len(replay)
     o._keep = keep  # keep the replay array alive with the options
+    if tuning is not None:
+        t = tuning if isinstance(tuning, RpmTuning) else RpmTuning(**tuning)
+        o.tuning = ctypes.pointer(t)
+        o._keep_tuning = t
     return o
 
 
@@ -194,6 +209,23 @@ def fft_apply(phase, lame_tab, lame0, E, eps, opts=None, workspace=None):
     if rc != 0:
         raise RpmError(rc, "rpm_fft_apply")
     return xi, err.value, np.array(sav[:])
+
+
+def autotune(phase, lame_tab, lame0, opts=None, reps=10, workspace=None):
+    """Launch shape of the pencil passes that maps fastest on this grid
+    (rpm_fft_autotune): dict(tuning=RpmTuning, ms=time per map, candidates=n)."""
+    opts = opts or make_options()
+    shape = tuple(phase.shape)
+    ws = workspace if workspace is not None else make_workspace(shape, opts)
+    pr = _problem(phase, lame_tab, lame0)
+    best = RpmTuning()
+    ms = ctypes.c_double()
+    nc = ctypes.c_int32()
+    rc = _lib.rpm_fft_autotune(ctypes.byref(pr), ctypes.byref(opts), int(reps), ctypes.byref(best), ctypes.byref(ms),
+                               ctypes.byref(nc), ws.data_ptr(), ws.numel(), _stream())
+    if rc != 0:
+        raise RpmError(rc, "rpm_fft_autotune")
+    return dict(tuning=best, ms=ms.value, candidates=nc.value)
 
 
 def fft_apply_static(phase, lame_tab, lame0, E, eps, opts=None, xi=None):

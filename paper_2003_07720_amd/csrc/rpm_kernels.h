@@ -1,7 +1,7 @@
 // Pass kernels of the gfx950 RPM-FFT path.
 //
-// One application of the Lippmann-Schwinger map (Algorithm 1 lines 5-9; the
-// operator F of Sec. 3) is five pencil passes over an FFT pipeline whose
+// One application of the Lippmann-Schwinger map (the iteration body of
+// Algorithm 1; the operator F of Sec. 3) is five pencil passes over an FFT pipeline whose
 // spectrum is transposed as it goes, so that every pass reads or writes whole
 // contiguous rows and the other side in 128-byte (or longer) segments:
 //

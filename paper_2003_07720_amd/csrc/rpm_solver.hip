@@ -140,13 +140,16 @@ struct Shapes {
     bool yip;                         // y passes transform in place (one LDS buffer)
     bool gip;                         // gamma pass transforms in place
     bool xip;                         // x passes transform in place
+    int Yb;                           // workgroups of the persistent y passes
     bool ok;
+    bool tune_ok;                     // the launch-shape overrides (rpm_tuning) apply to this grid
 };
 
 template <typename T>
-Shapes<T> make_shapes(const int32_t n[3], int ncomp)
+Shapes<T> make_shapes(const int32_t n[3], int ncomp, const rpm_tuning* tn = nullptr)
 {
     Shapes<T> s{};
+    s.tune_ok = true;
     const int wsz = (int)sizeof(cx<T>);
     const int MV = MaxV<T>::v;
     Geo& g = s.g;
@@ -173,6 +176,14 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     g.tz = largest_divisor_leq(g.nz, 128 / wsz);
     while (g.tz > 1 && (size_t)(2 * g.tz * lrow(g.ny) + g.ny) * wsz > (size_t)kLdsCap)
         g.tz = largest_divisor_leq(g.nz, g.tz - 1);
+    if (tn && tn->y_cols > 0) {
+        const int t = tn->y_cols;
+        if (g.nz % t != 0 || t > 128 / wsz || t * g.ny > 8 * kThreads ||
+            (size_t)(2 * t * lrow(g.ny) + g.ny) * wsz > (size_t)kLdsCap)
+            s.tune_ok = false;
+        else
+            g.tz = t;
+    }
     // 128-point y transforms of at most one butterfly per thread run in place
     s.yip = kYInPlace && g.ny == 128 && g.tz * 128 / 8 <= kThreads;
     s.lds_y = (size_t)((s.yip ? 1 : 2) * g.tz * lrow(g.ny) + g.ny) * wsz;
@@ -209,6 +220,9 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp)
     s.gip = s.gpipe && kGInPlace && nrow == 128 && ncomp * g.np * 128 / 8 <= kThreads;
     if (s.gip) s.lds_g = (size_t)(ncomp * np * lrow(nrow) + nrow) * wsz + 80 * 8;
     s.G3 = s.gpipe ? std::min(s.Gt, s.gip ? kGipBlocks : kGPipeBlocks) : s.Gt;  // gamma blocks (one error partial each)
+    s.Yb = s.yip ? kYipBlocks : kYPipeBlocks;
+    if (tn && tn->y_blocks > 0) s.Yb = tn->y_blocks;
+    if (tn && tn->gamma_blocks > 0 && s.gpipe) s.G3 = std::min(s.Gt, tn->gamma_blocks);
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
     s.Gp = (int)((6 * g.N + kVecBlock - 1) / kVecBlock);
     const long long ntile = (6 * g.N + kZTile - 1) / kZTile;
@@ -241,8 +255,6 @@ rpm_options basic_fp64_options(const rpm_options* o)
     return b;
 }
 
-template <typename T>
-Shapes<T> make_shapes(const int32_t n[3], int ncomp);
 
 // Spectral components carried by the forward passes: sigma, and eps too for
 // the polarization iteration.
@@ -276,7 +288,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o, bool map_only)
     L.twr = take(sizeof(cx<T>) * kMaxN);
     L.lame = take(sizeof(double) * 512);
     L.pmean = take(sizeof(double) * 6 * s.G1);
-    L.perr = take(sizeof(double) * s.G3);
+    L.perr = take(sizeof(double) * std::max(s.G3, s.Gt));  // any gamma grid (tuned or not) fits
     L.pinc = take(sizeof(double) * s.G1);
     L.pdots = take(sizeof(double) * 2 * L.ld * std::max(std::max(s.G1, s.Gp), s.Gq));
     const long long Gd = (6 * g.N + 4 * kThreads - 1) / (4 * kThreads);  // k_growth_diff blocks (3 partials each)
@@ -317,7 +329,7 @@ Layout make_layout(const Shapes<T>& s, const rpm_options* o, bool map_only)
             CaseOff& c = L.cs[f];
             c.st = take(sizeof(DevState));
             c.pmean = take(sizeof(double) * 6 * s.G1);
-            c.perr = take(sizeof(double) * s.G3);
+            c.perr = take(sizeof(double) * std::max(s.G3, s.Gt));
             c.pinc = take(sizeof(double) * s.G1);
             c.pdots = take(sizeof(double) * 2 * L.ld * std::max(std::max(s.G1, s.Gp), s.Gq));
             c.sums = take(sizeof(double) * (2 * kMaxP + 8));
@@ -536,10 +548,10 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         const int tiles = pol ? sh.Gyf : sh.Gy;
         c.mark_begin(RPM_K_YFWD, ev);
         if (kYPipe && sh.yip)
-            k_ypipe<T, -1, 8, true><<<std::min(tiles, kYipBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
+            k_ypipe<T, -1, 8, true><<<std::min(tiles, sh.Yb), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
                                                                                              c.twy(), tiles, done);
         else if (kYPipe && g.tz * g.ny <= 8 * kThreads)
-            k_ypipe<T, -1, 8, false><<<std::min(tiles, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
+            k_ypipe<T, -1, 8, false><<<std::min(tiles, sh.Yb), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
                                                                                                 c.twy(), tiles, done);
         else
             k_yfwd<T><<<tiles, kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py, c.twy(), done);
@@ -564,10 +576,10 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
         if (kYPipe && sh.yip)
-            k_ypipe<T, 1, 8, true><<<std::min(sh.Gy, kYipBlocks), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
+            k_ypipe<T, 1, 8, true><<<std::min(sh.Gy, sh.Yb), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
                                                                                             c.twy(), sh.Gy, done);
         else if (kYPipe && g.tz * g.ny <= 8 * kThreads)
-            k_ypipe<T, 1, 8, false><<<std::min(sh.Gy, kYPipeBlocks), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
+            k_ypipe<T, 1, 8, false><<<std::min(sh.Gy, sh.Yb), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
                                                                                                c.twy(), sh.Gy, done);
         else
             k_yinv<T><<<sh.Gy, kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py, c.twy(), done);
@@ -1332,6 +1344,8 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->batch_cases < 0 || o->batch_cases > 2) return RPM_E_INVALID;
     if (o->graph != 0 && o->graph != 1) return RPM_E_INVALID;
     if (o->profile_every < 0) return RPM_E_INVALID;
+    if (o->tuning && (o->tuning->y_cols < 0 || o->tuning->y_blocks < 0 || o->tuning->gamma_blocks < 0))
+        return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
         return RPM_E_INVALID;
@@ -1342,8 +1356,9 @@ template <typename T>
 rpm_status ctx_init(Ctx<T>& c, const rpm_problem* pr, const rpm_options* o, void* ws, size_t ws_bytes,
                     void* stream, bool map_only = false)
 {
-    c.sh = make_shapes<T>(pr->n, spectral_comps(o));
+    c.sh = make_shapes<T>(pr->n, spectral_comps(o), o->tuning);
     if (!c.sh.ok) return RPM_E_UNSUPPORTED_SIZE;
+    if (!c.sh.tune_ok) return RPM_E_INVALID;
     // FP32 fields are certified by an FP64 pipeline on the same grid
     if (sizeof(T) == 4 && !map_only && !make_shapes<double>(pr->n, spectral_comps(o)).ok)
         return RPM_E_UNSUPPORTED_SIZE;
@@ -1403,6 +1418,99 @@ rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_optio
     if (err) *err = hs.err;
     if (sig_avg)
         for (int i = 0; i < 6; ++i) sig_avg[i] = hs.sig_hat0[i] / (double)c.sh.g.N;
+    return RPM_OK;
+}
+
+// Tile autotuner: times the map under candidate launch shapes (coordinate
+// search over y_cols, y_blocks, gamma_blocks; 0 = default first).
+template <typename T>
+rpm_status tune_typed(const rpm_problem* pr, const rpm_options* o, int reps, rpm_tuning* best, double* best_ms,
+                      int32_t* ncand, void* ws, size_t ws_bytes, void* stream)
+{
+    rpm_options ob = *o;
+    ob.tuning = nullptr;
+    ob.profile = 0;
+    Ctx<T> c;
+    rpm_status rs = ctx_init(c, pr, &ob, ws, ws_bytes, stream);
+    if (rs != RPM_OK) return rs;
+    int p = 0;
+    rs = prepare(c, pr, &ob, false, &p, ob.tol);
+    if (rs != RPM_OK) return rs;
+    const double E[6] = {0.01, 0.0, 0.0, 0.0, 0.0, 0.0};
+    set_E(c, E);
+    const Geo& g0 = c.sh.g;
+    k_fill_uniform<T><<<(int)((6 * g0.N + 255) / 256), 256, 0, c.s>>>(c.eps(), c.st->E, g0.N);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return RPM_E_HIP;
+    }
+    const Shapes<T> base = c.sh;
+    int count = 0;
+    bool hip_ok = true;
+    // ms per map of one shape; < 0 when the shape does not apply to the grid
+    auto time_shape = [&](const rpm_tuning& tn) -> double {
+        const Shapes<T> sh = make_shapes<T>(pr->n, spectral_comps(&ob), &tn);
+        if (!sh.ok || !sh.tune_ok) return -1.0;
+        c.sh = sh;
+        run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(0), OUT_XI, 0, DC_MEAN, c.st->E, nullptr);
+        hipEventRecord(e0, c.s);
+        for (int r = 0; r < reps; ++r)
+            run_F<T>(c, c.eps(), 0, nullptr, c.eps(), c.ring(0), OUT_XI, 0, DC_MEAN, c.st->E, nullptr);
+        hipEventRecord(e1, c.s);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess || c.hip_error)
+            hip_ok = false;
+        c.sh = base;
+        ++count;
+        return hip_ok ? (double)ms / reps : -1.0;
+    };
+    rpm_tuning cur{0, 0, 0};
+    double cur_ms = time_shape(cur);
+    const Geo& g = base.g;
+    // y_cols: admissible divisors of nz, largest first (3-D only)
+    if (!g.two_d) {
+        int tried = 0;
+        for (int t = std::min(g.nz, 64); t >= 1 && tried < 4 && hip_ok; --t) {
+            if (g.nz % t != 0 || t == g.tz) continue;
+            rpm_tuning tn = cur;
+            tn.y_cols = t;
+            const Shapes<T> sh = make_shapes<T>(pr->n, spectral_comps(&ob), &tn);
+            if (!sh.ok || !sh.tune_ok) continue;
+            ++tried;
+            const double ms = time_shape(tn);
+            if (ms >= 0.0 && ms < cur_ms) {
+                cur = tn;
+                cur_ms = ms;
+            }
+        }
+    }
+    const int mult[7] = {1, 2, 3, 4, 5, 6, 8};
+    // y_blocks, then gamma_blocks: 256 x mult, below the tile counts
+    for (int coord = 0; coord < 2 && hip_ok; ++coord) {
+        if (coord == 0 && g.two_d) continue;
+        const Shapes<T> sh0 = make_shapes<T>(pr->n, spectral_comps(&ob), &cur);
+        if (coord == 1 && !sh0.gpipe) continue;  // one tile per workgroup: nothing to tune
+        const int tiles = coord == 0 ? sh0.Gy : sh0.Gt;
+        for (int m = 0; m < 7 && hip_ok; ++m) {
+            const int b = 256 * mult[m];
+            if (b > tiles) break;
+            rpm_tuning tn = cur;
+            if (coord == 0) tn.y_blocks = b;
+            else tn.gamma_blocks = b;
+            const double ms = time_shape(tn);
+            if (ms >= 0.0 && ms < cur_ms) {
+                cur = tn;
+                cur_ms = ms;
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (!hip_ok || cur_ms < 0.0) return RPM_E_HIP;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    if (ncand) *ncand = count;
     return RPM_OK;
 }
 
@@ -1888,6 +1996,7 @@ void rpm_default_options(rpm_options* o)
     o->batch_cases = 0;
     o->graph = 0;
     o->profile_every = 1;
+    o->tuning = nullptr;
 }
 
 rpm_status rpm_lame_from_young(double E, double nu, double* lam, double* mu)
@@ -1930,6 +2039,17 @@ rpm_status rpm_fft_apply(const rpm_problem* pr, const double E[6], const rpm_opt
     if (o->precision == RPM_FP64)
         return apply_typed<double>(pr, E, o, eps, xi, err, sig_avg, workspace, ws_bytes, hip_stream);
     return apply_typed<float>(pr, E, o, eps, xi, err, sig_avg, workspace, ws_bytes, hip_stream);
+}
+
+rpm_status rpm_fft_autotune(const rpm_problem* pr, const rpm_options* o, int32_t reps, rpm_tuning* best,
+                            double* best_ms, int32_t* candidates, void* workspace, size_t ws_bytes, void* hip_stream)
+{
+    rpm_status rs = validate(pr, o);
+    if (rs != RPM_OK) return rs;
+    if (!best || reps < 1 || reps > 1000) return RPM_E_INVALID;
+    if (o->precision == RPM_FP64)
+        return tune_typed<double>(pr, o, reps, best, best_ms, candidates, workspace, ws_bytes, hip_stream);
+    return tune_typed<float>(pr, o, reps, best, best_ms, candidates, workspace, ws_bytes, hip_stream);
 }
 
 rpm_status rpm_fft_apply_static(const rpm_problem* pr, const double E[6], const rpm_options* o, const void* eps,

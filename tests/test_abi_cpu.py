@@ -43,7 +43,7 @@ def test_default_options_and_status_strings(B):
     assert o.tol == 1e-6 and o.max_iter == 10000 and o.n_max == 10 and o.p_max == 32
     assert abs(o.kappa - 0.1) < 1e-15 and o.scheme == 1 and o.precision == 0 and o.check_every == 16
     assert o.map == 0 and o.alpha == 2.0 and o.beta == 2.0
-    assert o.profile == 0 and o.profile_classes == 0 and o.profile_every == 1
+    assert o.profile == 0 and o.profile_classes == 0 and o.profile_every == 1 and not o.tuning
     for code, name in B.STATUS.items():
         assert B.status_string(code) == name
     assert B.status_string(99) == "RPM_UNKNOWN"
@@ -101,7 +101,8 @@ def _raw_problem(B, n=(8, 8, 8), lame=((1.0, 1.0),), lame0=(1.0, 1.0)):
 
 
 @pytest.mark.parametrize("case", ["tol", "nan_E", "pmax", "mu0", "neg_mu", "scheme", "check", "size", "nphase",
-                                  "workspace", "kappa", "replay", "map", "alpha", "classes", "every"])
+                                  "workspace", "kappa", "replay", "map", "alpha", "classes", "every", "tune_neg",
+                                  "tune_cols", "tune_wide"])
 def test_solve_rejects_bad_arguments_before_device_work(B, case):
     lib = B._lib
     o = B.make_options()
@@ -146,6 +147,16 @@ def test_solve_rejects_bad_arguments_before_device_work(B, case):
     elif case == "every":
         o.profile = 1
         o.profile_every = -2
+    elif case == "tune_neg":
+        tn = B.RpmTuning(0, -256, 0)
+        o.tuning = ctypes.pointer(tn)
+    elif case == "tune_cols":  # not a divisor of nz = 8
+        tn = B.RpmTuning(3, 0, 0)
+        o.tuning = ctypes.pointer(tn)
+    elif case == "tune_wide":  # more z positions per y tile than the pass holds
+        tn = B.RpmTuning(64, 0, 0)
+        pr = _raw_problem(B, n=(64, 64, 64))
+        o.tuning = ctypes.pointer(tn)
     rc = lib.rpm_fft_solve(ctypes.byref(pr), E, ctypes.byref(o), None, None, None, None, None, ws, wsb, None)
     assert rc == expect, (case, rc)
     rc = lib.rpm_fft_effective_tensor(ctypes.byref(pr), ctypes.byref(o), (ctypes.c_double * 36)(), None, ws, wsb,
@@ -231,3 +242,28 @@ def test_apply_static_rejects_before_device_work(B):
     o = B.make_options(precision="fp64")  # 128^3 spectra in FP64 exceed the array
     assert lib.rpm_fft_apply_static(ctypes.byref(big), E, ctypes.byref(o), 0x3000, 0x4000, None, None, None) == -6
     assert B.status_string(-6) == "RPM_E_SCRATCH"
+
+
+@pytest.mark.parametrize("case", ["reps0", "reps_big", "no_best", "bad_tuning_ignored"])
+def test_autotune_rejects_bad_arguments(B, case):
+    """rpm_fft_autotune validates before any device work; o->tuning is ignored."""
+    lib = B._lib
+    o = B.make_options()
+    pr = _raw_problem(B)
+    best = B.RpmTuning()
+    reps, bp = 5, ctypes.byref(best)
+    ws, wsb = 0x2000, 1 << 40
+    expect = -1
+    if case == "reps0":
+        reps = 0
+    elif case == "reps_big":
+        reps = 1001
+    elif case == "no_best":
+        bp = None
+    elif case == "bad_tuning_ignored":
+        tn = B.RpmTuning(3, 0, 0)  # would be rejected by a solve
+        o.tuning = ctypes.pointer(tn)
+        ws, wsb = None, 0
+        expect = -3  # the workspace check is reached: the tuning was not applied
+    rc = lib.rpm_fft_autotune(ctypes.byref(pr), ctypes.byref(o), reps, bp, None, None, ws, wsb, None)
+    assert rc == expect, (case, rc)
