@@ -179,10 +179,10 @@ typedef struct {
                                  profile = 1 or a NULL stream, which cannot be
                                  captured); 0 = kernel by kernel                 */
     int32_t profile_every;    /* with profile = 1: events around one launch in
-                                 every this many of each class (the first, then
-                                 every profile_every-th), so a long timed solve
-                                 carries few event records; 0 or 1 = every
-                                 launch (>= 0)                                   */
+                                 every this many of each class (the
+                                 profile_every-th, the 2 profile_every-th, ...),
+                                 so a long timed solve carries few event
+                                 records; 0 or 1 = every launch (>= 0)           */
     const struct rpm_tuning_s *tuning; /* HOST, nullable: launch shape of the
                                  pencil passes (rpm_fft_autotune); NULL = the
                                  library's defaults.  The workspace size does

@@ -459,7 +459,7 @@ struct Ctx {
     {
         a = nullptr;
         if (!prof.on || !((prof.mask >> k) & 1u)) return;
-        if (prof.seen[k]++ % prof.every != 0) return;
+        if (prof.seen[k]++ % prof.every != prof.every - 1) return;  // the every-th, 2 every-th, ... launch
         a = prof.get();
         if (a) hipEventRecord(a, s);
     }
