@@ -621,6 +621,25 @@ def disk32_row(B, M, torch):
                                                  candidates=t["candidates"], tune_seconds=round(tune_s, 3),
                                                  ms_per_map_solve_default=ms["default"],
                                                  ms_per_map_solve_tuned=ms["tuned"])
+    # the batched family: seeded two-phase cells of uneven grids, the six unit
+    # load cases each (FP32, FP64 refinement, tol 1e-6), one worker against four
+    # and eight concurrent workers (a stream each), launch shapes tuned per grid
+    from paper_2003_07720_amd import batch as bt
+
+    cells = bt.random_cells(16, grids=(32, 48, 64), seed0=0, contrast=(1e-3, 1e2))
+    kw = dict(scheme="rpm", precision="fp32", tol=1e-6, refine=4, p_max=32, max_iter=20000, check_every=32)
+    t0 = time.perf_counter()
+    tunings = bt.tune_grids(cells, kw, reps=10)
+    tune_s = time.perf_counter() - t0
+    row = dict(cells=len(cells), grids=sorted({c["n"] for c in cells}), tune_seconds=round(tune_s, 3),
+               tunings={f"{k[0]}^3": v.as_dict() for k, v in tunings.items()})
+    for workers in (1, 4, 8):
+        res, wall = bt.effective_many(cells, kw, workers=workers, tunings=tunings)
+        row[f"workers{workers}"] = dict(seconds=round(wall, 3), cells_per_s=round(len(cells) / wall, 3),
+                                        statuses=sorted({r["status"] for r in res}),
+                                        max_residual_fp64=max(r["residual_fp64"] for r in res),
+                                        map_applications=sum(sum(r["iterations"]) + r["jvps"] for r in res))
+    out["batched_cells_32_48_64"] = row
     print(f"bench: small configurations {out}", file=sys.stderr, flush=True)
     return out
 
