@@ -151,6 +151,10 @@ def parse():
     ap.add_argument("--stress", action="store_true",
                     help="instead of the benchmark: a prescribed-mean-stress solve of the 64^3 sphere workload "
                          "(FP64 and FP32 refined), timed; prints its own JSON line")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark: the 64^3 sphere C_eff over the five reference media between "
+                         "the phase moduli, FP64 and FP32 refined (RPM p_max 64), and Algorithm 1 on the zz case; "
+                         "prints its own JSON line")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn two rocprofv3 --pmc counter files (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --warmup 0 --no-cpu --no-ttt --no-small --no-warm --calibrate-copy-mib M' into "
@@ -246,6 +250,64 @@ def stress_bench():
                       "rows": rows}), flush=True)
 
 
+def sweep_bench():
+    """The 64^3 sphere workload's effective tensor for each reference medium of
+    the 5-point sweep between the phase moduli (E0 = 1 ... 1000): RPM (p_max 64,
+    tol 1e-6) with FP64 fields and with FP32 fields refined to FP64-certified
+    1e-6, each timed after an untimed call; and Algorithm 1 alone on the zz
+    load case (FP64, 20 000 steps at most), whose map diverges for E0 below
+    half the stiff modulus."""
+    import torch
+
+    from paper_2003_07720_amd import binding as B
+    from paper_2003_07720_amd import microstructure as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    rows = []
+    for ri in range(5):
+        w = M.workload_spheres64(ref_index=ri)
+        phase = torch.from_numpy(w["phase"]).to("cuda")
+        lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
+        l0 = B.lame_from_young(*w["ref"])
+        row = dict(E0=w["ref"][0])
+        Cs = {}
+        for prec in ("fp64", "fp32"):
+            opts = B.make_options(scheme="rpm", precision=prec, tol=1e-6, n_max=10, p_max=64, check_every=32,
+                                  max_iter=20000)
+            ws = B.make_workspace(tuple(phase.shape), opts)
+            B.effective_tensor(phase, lt, l0, opts, workspace=ws, history_cap=20001)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C, stats, st = B.effective_tensor(phase, lt, l0, opts, workspace=ws, history_cap=20001)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            Cs[prec] = C
+            row[prec] = dict(status=st, seconds=round(el, 3), iterations=[x["iterations"] for x in stats],
+                             jvps=sum(x["jvps"] for x in stats),
+                             residual_fp64=max(x["residual_fp64"] for x in stats),
+                             C11=C[0][0], C12=C[0][1], C33=C[2][2], C44=C[3][3])
+            print(f"sweep: E0 {w['ref'][0]} {prec} {row[prec]}", file=sys.stderr, flush=True)
+        row["fp32_vs_fp64_max_rel"] = float(np.abs(Cs["fp32"] - Cs["fp64"]).max() / np.abs(Cs["fp64"]).max())
+        ob = B.make_options(scheme="basic", precision="fp64", tol=1e-6, check_every=32, max_iter=20000)
+        wb = B.make_workspace(tuple(phase.shape), ob)
+        t0 = time.perf_counter()
+        rb = B.fft_solve(phase, lt, l0, np.array([0, 0, 0.01, 0, 0, 0.0]), ob, workspace=wb, want_eps=False,
+                         history_cap=20001)
+        torch.cuda.synchronize()
+        h = rb["history"]
+        row["basic_zz_fp64"] = dict(status=rb["status"], iterations=rb["iterations"], residual=rb["residual"],
+                                    seconds=round(time.perf_counter() - t0, 3),
+                                    error_at={str(k): float(h[k]) for k in (10, 100, 1000, 10000) if k < len(h)})
+        print(f"sweep: E0 {w['ref'][0]} basic {row['basic_zz_fp64']}", file=sys.stderr, flush=True)
+        rows.append(row)
+    print(json.dumps({"metric": "seconds per 6x6 effective tensor over the reference-medium sweep, 64^3 spheres",
+                      "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "64^3 random spheres (radii 4-8, vf 0.2, seed 2000), E 1 / 1000 "
+                                             "(nu 0.3 / 0.25), E0 on the 5-point linear sweep 1 ... 1000, RPM "
+                                             "p_max 64, n_max 10, tol 1e-6"},
+                      "rows": rows}), flush=True)
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -329,6 +391,9 @@ def main():
         return
     if a.stress and a.gpus == 1:
         stress_bench()
+        return
+    if a.sweep and a.gpus == 1:
+        sweep_bench()
         return
     if a.gpus != 1:
         print(f"bench.py: --gpus {a.gpus} refused: the benchmark runs on a single GPU (one process, one device); "
