@@ -729,6 +729,14 @@ def disk32_row(B, M, torch):
                                         statuses=sorted({r["status"] for r in res}),
                                         max_residual_fp64=max(r["residual_fp64"] for r in res),
                                         map_applications=sum(sum(r["iterations"]) + r["jvps"] for r in res))
+    # the same batch with FP64 fields: on grids this small a pass costs its
+    # launch, not its bytes, so FP32 saves nothing and its refinement adds work
+    kw64 = dict(kw, precision="fp64")
+    res, wall = bt.effective_many(cells, kw64, workers=4, tunings=bt.tune_grids(cells, kw64, reps=10))
+    row["fp64_workers4"] = dict(seconds=round(wall, 3), cells_per_s=round(len(cells) / wall, 3),
+                                statuses=sorted({r["status"] for r in res}),
+                                max_residual_fp64=max(r["residual_fp64"] for r in res),
+                                map_applications=sum(sum(r["iterations"]) + r["jvps"] for r in res))
     out["batched_cells_32_48_64"] = row
     print(f"bench: small configurations {out}", file=sys.stderr, flush=True)
     return out
