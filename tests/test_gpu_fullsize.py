@@ -110,6 +110,37 @@ def test_rpm_trajectory_voids128_fp32(B, voids128):
     np.testing.assert_allclose(g["history"], ref["history"], rtol=1e-4)
 
 
+def test_steady_state_iterate_voids128_fp32(B, voids128):
+    """The benchmark's configuration at its steady state: the basis built to
+    p = 32 by a 400-step solve, then 20 steps carrying it (the x pass
+    recombining eps = xi + Z d on the way in).  The last iterate the GPU
+    returns is mapped by the FP64 oracle: its equilibrium error and mean stress
+    must be what the GPU computed for that same field (FP32 FFT rounding:
+    1e-4 relative on the error, 1e-5 on <sigma>)."""
+    w = voids128
+    print("steady-state iterate 128^3 voids fp32", flush=True)
+    E0 = 0.5 * (w["phases"][0][0] + w["phases"][1][0])
+    lt = np.array([B.lame_from_young(*p) for p in w["phases"]])
+    l0 = B.lame_from_young(E0, 0.3)
+    common = dict(scheme="rpm", precision="fp32", n_max=10, p_max=32, kappa=0.1, check_every=32, refine=0)
+    ph = dev(w["phase"])
+    ws = B.make_workspace(ph.shape, B.make_options(max_iter=401, **common))
+    rb = B.fft_solve(ph, lt, l0, w["E"], B.make_options(max_iter=400, tol=1e-6, **common), workspace=ws,
+                     want_eps=False)
+    assert rb["basis_dim"] == 32
+    g = B.fft_solve(ph, lt, l0, w["E"], B.make_options(max_iter=20, tol=1e-15, reuse_basis=1, **common),
+                    workspace=ws)
+    assert g["iterations"] == 20 and g["basis_dim"] == 32 and g["jvps"] == 0
+    eps = g["eps"].double().cpu().numpy()
+    _, err, sav, _ = O.fmap(w["phase"], O.lame_table(w["phases"]), O.lame(E0, 0.3), w["E"], eps)
+    print(f"GPU error {g['history'][-1]:.6e} oracle {err:.6e}", flush=True)
+    print(f"GPU FP64 evaluation of the same field {g['residual_fp64']:.6e}", flush=True)
+    assert abs(g["history"][-1] - err) <= 1e-4 * err
+    assert np.abs(g["sig_avg"] - sav).max() <= 1e-5 * np.abs(sav).max()
+    # the FP64 evaluation of the returned field (certification pipeline) is the oracle's to rounding
+    assert abs(g["residual_fp64"] - err) <= 1e-9 * err
+
+
 def test_effective_tensor_3d_fp64(B):
     """6x6 effective stiffness of a 16^3 cell with 7 spheres (contrast 20) against the
     oracle, the basis carried across load cases on both sides."""
