@@ -623,13 +623,14 @@ def learned_warm_start(a, B, M, torch):
     for tol in [float(x) for x in a.ttt_loose.split(",") if x] + [a.tol]:
         rows[f"{tol:g}"] = S.compare_warm_start(cfg, params, w["phase"], w["phases"], w["E"], tol,
                                                 precision=a.precision, ref=(0.5 * (1 + 1e-8), 0.3),
-                                                max_iter=min(a.ttt_iters, 1000) if tol == a.tol else a.ttt_iters)
+                                                max_iter=min(a.ttt_iters, 1000) if tol == a.tol else a.ttt_iters,
+                                                seeded=tol != a.tol)
     out["voids128"] = rows
     # where 1e-6 is reachable: void stiffness 1e-3, E0 at the matrix modulus,
     # FP32 refined with p_max 64 (the fastest plain configuration there)
     out["voids128_stiffness_1e-3"] = S.compare_warm_start(cfg, params, w["phase"], [(1.0, 0.3), (1e-3, 0.3)], w["E"],
                                                           a.tol, precision="fp32", p_max=64, ref=(1.0, 0.3),
-                                                          max_iter=30000)
+                                                          max_iter=30000, seeded=True)
     print(f"bench: learned warm start {out}", file=sys.stderr, flush=True)
     return out
 

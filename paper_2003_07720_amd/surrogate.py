@@ -108,22 +108,34 @@ def relative_error(cfg, params, X, Y):
     return (num / den) ** 0.5
 
 
-def compare_warm_start(cfg, params, ph, phases, E, tol, precision="fp64", p_max=32, max_iter=20000, ref=None):
+def compare_warm_start(cfg, params, ph, phases, E, tol, precision="fp64", p_max=32, max_iter=20000, ref=None,
+                       seeded=False):
     """Iterations and seconds of plain RPM against RPM from the network's warm
-    start (network evaluation included in the time), each after an untimed run."""
+    start (network evaluation included in the time), each after an untimed run.
+    seeded: also the warm start with the basis seeded by the network's six
+    predicted unit-case fluctuations (rpm_fft_seed_basis, then reuse_basis)."""
     dph = torch.from_numpy(np.ascontiguousarray(ph)).to("cuda")
     lt = np.array([B.lame_from_young(*p) for p in phases])
     l0 = B.lame_from_young(*(ref or reference_medium(phases)))
-    opts = B.make_options(precision=precision, tol=tol, max_iter=max_iter, p_max=p_max, check_every=32)
+    kw = dict(precision=precision, tol=tol, max_iter=max_iter, p_max=p_max, check_every=32)
+    opts = B.make_options(**kw)
     ws = B.make_workspace(tuple(ph.shape), opts)
     fws = B.fno_workspace(cfg, tuple(ph.shape), 1)
+    dt = torch.float64 if precision == "fp64" else torch.float32
     out = {}
-    for mode in ("plain", "warm"):
+    for mode in ("plain", "warm") + (("warm_seeded",) if seeded else ()):
         for rep in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            eps0 = B.fno_warm_start(cfg, params, dph, lt, l0, E, precision, fws) if mode == "warm" else None
-            r = B.fft_solve(dph, lt, l0, E, opts, eps0=eps0, workspace=ws, want_eps=False)
+            eps0 = B.fno_warm_start(cfg, params, dph, lt, l0, E, precision, fws) if mode != "plain" else None
+            o = opts
+            if mode == "warm_seeded":
+                x = B.fno_features(dph, lt)
+                y, _ = B.fno_forward(cfg, params, x[None].contiguous(), fws)
+                V = y[0].view(6, 6, *dph.shape).to(dt).contiguous()
+                B.seed_basis(dph, lt, l0, V, opts, ws)
+                o = B.make_options(reuse_basis=1, **kw)
+            r = B.fft_solve(dph, lt, l0, E, o, eps0=eps0, workspace=ws, want_eps=False)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
         out[mode] = dict(status=r["status"], iterations=r["iterations"], jvps=r["jvps"], seconds=round(el, 4),
