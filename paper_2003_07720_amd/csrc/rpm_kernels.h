@@ -39,6 +39,10 @@ __device__ __forceinline__ double2 nt_load(const double2* p)
     return make_double2(t.x, t.y);
 }
 
+// waves per SIMD the compiler budgets registers for: the in-place gamma pass
+// (five resident blocks per CU), and the x pass that recombines eps = xi + Z d
+// on the way in (four; with 8 basis columns in flight per lane it needs ~114
+// VGPRs, and 16 columns spill at four waves and drop to three)
 #ifndef RPM_GIP_WPE
 #define RPM_GIP_WPE 5
 #endif
