@@ -6,8 +6,8 @@
  * tensor).  A solve for the mean strain E then starts (rpm_fft_solve's eps0)
  * from E plus the predicted fluctuation instead of the uniform E with which
  * Algorithm 2 of Peng, Nepal & Dayal (CMAME 2020) starts; the iteration and its
- * equilibrium error stay the judge of the result, so a poor prediction only
- * costs iterations.  The network is not part of the paper.
+ * equilibrium error still decide when the result is accepted, so a poor
+ * prediction only costs iterations.  The network is not part of the paper.
  *
  * Network (x: per-voxel features, C = width, L = layers, m = modes):
  *   h_0     = W_lift x + b_lift

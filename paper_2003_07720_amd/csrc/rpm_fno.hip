@@ -3,8 +3,8 @@
 // the six unit load cases (the localization tensor), so that a solve for a
 // mean strain E can start from E plus the predicted fluctuation instead of the
 // uniform E of Algorithm 2's initialization.  The network and its training
-// are not in the paper; they sit in front of the method, which stays the judge
-// of the result through its own equilibrium error.
+// are not in the paper; they sit in front of the method, whose own equilibrium
+// error still decides when the result is accepted.
 //
 // Network (per voxel features x, C hidden channels, L spectral layers):
 //   h_0     = W_lift x + b_lift
