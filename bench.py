@@ -609,7 +609,8 @@ def learned_warm_start(a, B, M, torch):
     Xv, Yv, _ = S.make_dataset(32, 8, 100000)
     t1 = time.perf_counter()
     cfg = B.fno_config(2, 36, 32, 4, 12)
-    params, hist = S.train(cfg, X, Y, steps=a.warm_steps, batch=4, lr=3e-3, seed=1, log_every=0)
+    params, hist = S.train(cfg, X, Y, steps=a.warm_steps, batch=4, lr=3e-3, seed=1,
+                           log_every=500 if a.warm_steps > 1000 else 0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     out = dict(network="FNO: 2 features -> width 32, 4 spectral layers, 12 signed modes per axis -> 36 channels; "

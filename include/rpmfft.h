@@ -254,8 +254,8 @@ rpm_status rpm_fft_apply(const rpm_problem *pr, const double E[6], const rpm_opt
  *   best_ms   HOST nullable: its time per map application
  *   candidates HOST nullable: number of shapes timed
  * o->tuning is ignored.  The workspace holds rpm_workspace_size(n, o) bytes;
- * its fields and basis are overwritten (the stored basis is kept only if the
- * same workspace is not tuned: call this before the solves that reuse it).
+ * its fields are overwritten and any basis it holds is dropped, so tune before
+ * the solves that would carry a basis in it (reuse_basis).
  * Errors as rpm_fft_apply; RPM_E_INVALID for reps out of range or NULL best.
  */
 rpm_status rpm_fft_autotune(const rpm_problem *pr, const rpm_options *o, int32_t reps, rpm_tuning *best,

@@ -11,6 +11,7 @@ iterates to its own tolerance, so the network can only save iterations.
 """
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -60,14 +61,19 @@ def solve_targets(ph, phases, tol=1e-6, max_iter=20000, p_max=64):
     return x, y, its
 
 
-def make_dataset(n, count, seed0=0, **kw):
+def make_dataset(n, count, seed0=0, log_every=16, **kw):
+    """Features and targets of `count` seeded cells (progress on stderr every
+    log_every cells; 0 = quiet)."""
     xs, ys, info = [], [], []
-    for s in range(seed0, seed0 + count):
+    t0 = time.perf_counter()
+    for k, s in enumerate(range(seed0, seed0 + count)):
         ph, phases, inf = random_cell(n, s, **kw)
         x, y, its = solve_targets(ph, phases)
         xs.append(x)
         ys.append(y)
         info.append(dict(seed=s, contrast=phases[1][0], vf=inf["vf"], iterations=its))
+        if log_every and (k + 1) % log_every == 0:
+            print(f"fno data: {k + 1}/{count} cells ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
     return torch.stack(xs), torch.stack(ys), info
 
 
@@ -93,7 +99,8 @@ def train(cfg, X, Y, steps=400, batch=4, lr=2e-3, seed=0, log_every=50):
         loss = B.fno_train_step(cfg, params, grad, m, v, step, float(max(lr_t, 1e-5)), xb, yb, ws)
         hist.append(loss)
         if log_every and step % log_every == 0:
-            print(f"fno train: step {step} loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)", flush=True)
+            print(f"fno train: step {step} loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)", file=sys.stderr,
+                  flush=True)
     return params, hist
 
 
