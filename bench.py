@@ -136,6 +136,9 @@ def parse():
     ap.add_argument("--no-warm", action="store_true", help="skip training and timing the learned warm start")
     ap.add_argument("--warm-cells", type=int, default=64, help="solver-generated training cells (32^3)")
     ap.add_argument("--warm-steps", type=int, default=800, help="training steps of the warm-start network")
+    ap.add_argument("--warm-eval-cells", type=int, default=0,
+                    help="also evaluate the warm start on this many held-out 128^3 void cells (other seeds, void "
+                         "stiffness 1e-3, to the tolerance)")
     ap.add_argument("--cpu-steps", type=int, default=14, help="oracle map applications in the CPU sample")
     ap.add_argument("--cpu-c2-maps", type=int, default=4,
                     help="single-threaded oracle map applications sampled on the 64^3 spheres")
@@ -632,6 +635,23 @@ def learned_warm_start(a, B, M, torch):
     out["voids128_stiffness_1e-3"] = S.compare_warm_start(cfg, params, w["phase"], [(1.0, 0.3), (1e-3, 0.3)], w["E"],
                                                           a.tol, precision="fp32", p_max=64, ref=(1.0, 0.3),
                                                           max_iter=30000, seeded=True)
+    if a.warm_eval_cells > 0:
+        # held-out void cells of the same recipe (other seeds), void stiffness 1e-3 so the tolerance is reachable
+        ev = []
+        for k in range(a.warm_eval_cells):
+            wk = M.workload_voids128(seed=a.seed + 1 + k, n=a.n)
+            r = S.compare_warm_start(cfg, params, wk["phase"], [(1.0, 0.3), (1e-3, 0.3)], wk["E"], a.tol,
+                                     precision="fp32", p_max=64, ref=(1.0, 0.3), max_iter=30000)
+            ev.append(dict(seed=a.seed + 1 + k, plain=r["plain"], warm=r["warm"]))
+            print(f"bench: held-out cell {k}: {r}", file=sys.stderr, flush=True)
+        ok = [e for e in ev if e["plain"]["status"] == "RPM_OK" and e["warm"]["status"] == "RPM_OK"]
+        out["heldout_voids128_stiffness_1e-3"] = dict(
+            cells=len(ev), both_converged=len(ok),
+            mean_iterations_plain=float(np.mean([e["plain"]["iterations"] for e in ok])) if ok else None,
+            mean_iterations_warm=float(np.mean([e["warm"]["iterations"] for e in ok])) if ok else None,
+            mean_seconds_plain=float(np.mean([e["plain"]["seconds"] for e in ok])) if ok else None,
+            mean_seconds_warm=float(np.mean([e["warm"]["seconds"] for e in ok])) if ok else None,
+            per_cell=ev)
     print(f"bench: learned warm start {out}", file=sys.stderr, flush=True)
     return out
 
