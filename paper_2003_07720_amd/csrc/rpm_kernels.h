@@ -1043,16 +1043,16 @@ struct Fields {
 // same field slice (one HBM read, the rest from cache).  Slices are addressed
 // as a wave-uniform base plus the lane offset.  Partial sums are
 // column-major: part[(f * ld + j) * G + b], G = gridDim.x.
-template <bool FULL, typename TA, typename TZ, int NF, bool NT>
+template <bool FULL, typename TA, typename TZ, int NF, bool NT, int C = 8>
 __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, const TZ* __restrict__ zt, int lo,
                                            int nj, long long e0, long long L6, long long N3,
-                                           double (&acc)[NF][8])
+                                           double (&acc)[NF][C])
 {
     double w[4], fv[NF][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) w[u] = (FULL || e0 + u < L6) ? (e0 + u < N3 ? 1.0 : 2.0) : 0.0;
     Raw4<TA> ra[NF];
-    Raw4<TZ> raw[8];
+    Raw4<TZ> raw[C];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         if (FULL) ra[f].load(a.f[f] + t0 + lo);
@@ -1061,7 +1061,7 @@ __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, co
     // slots past the group's last column repeat it (valid memory); their sums
     // are never stored
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < C; ++u) {
         const TZ* zc = zt + (long long)min(u, nj - 1) * kZTile;
         if (FULL) raw[u].template load_s<NT>(zc + lo);
         else raw[u].load_tail(zc + lo, e0, L6);
@@ -1073,7 +1073,7 @@ __device__ __forceinline__ void gdots_tile(const Fields<TA>& a, long long t0, co
         for (int q = 0; q < 4; ++q) fv[f][q] *= w[q];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < C; ++u) {
         double z[4];
         raw[u].get(z);
 #pragma unroll
@@ -1112,6 +1112,86 @@ __global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restric
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
+            const double sum = wave_sum(acc[f][u]);
+            if (lane == 0 && u < nj) part[(long long)(f * ld + j0 + u) * gridDim.x + blockIdx.x] = sum;
+        }
+}
+
+#ifndef RPM_GS_CPW
+#define RPM_GS_CPW 2
+#endif
+#ifndef RPM_GS_TPB
+#define RPM_GS_TPB 8
+#endif
+// The per-step products with the columns split finer: a wave owns C columns
+// (the block has ceil(p / C) <= 16 waves) and streams their slices of TB
+// consecutive tiles per round (C * TB loads issued together), so the block's
+// waves read each group of tiles' slices of all columns, one contiguous
+// region, together.  Same partial-sum layout as k_gdots.
+template <typename TA, typename TZ, int NF, int SITE, int C = RPM_GS_CPW, int TB = RPM_GS_TPB>
+__global__ __launch_bounds__(1024) void k_gdots_split(Fields<TA> a, const TZ* __restrict__ Z, int p, int zP,
+                                                      long long N, double* __restrict__ part, int ld)
+{
+    const int lane = threadIdx.x & 63;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int j0 = C * g;
+    const int nj = min(C, p - j0);  // >= 1: the block has ceil(p / C) waves
+    const int lo = 4 * lane;
+    const long long L6 = 6 * N, N3 = 3 * N;
+    const long long nfull = L6 / kZTile;
+    const long long ngrp = nfull / TB;
+    double acc[NF][C];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int u = 0; u < C; ++u) acc[f][u] = 0.0;
+    for (long long grp = blockIdx.x; grp < ngrp; grp += gridDim.x) {
+        const long long t0 = grp * TB;
+        Raw4<TA> ra[TB][NF];
+        Raw4<TZ> raw[TB][C];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) ra[t][f].load(a.f[f] + (t0 + t) * kZTile + lo);
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+                raw[t][u].template load_s<true>(Z + ((t0 + t) * zP + j0 + min(u, nj - 1)) * (long long)kZTile + lo);
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            const long long e0 = (t0 + t) * kZTile + lo;
+            double fv[NF][4];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                ra[t][f].get(fv[f]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fv[f][q] *= (e0 + q < N3 ? 1.0 : 2.0);
+            }
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                double z[4];
+                raw[t][u].get(z);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) acc[f][u] += z[q] * fv[f][q];
+            }
+        }
+    }
+    // tiles past the last whole group, then the last, partial tile
+    for (long long tile = ngrp * TB + blockIdx.x; tile <= nfull; tile += gridDim.x) {
+        if (tile < nfull)
+            gdots_tile<true, TA, TZ, NF, true, C>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo, nj,
+                                                  tile * kZTile + lo, L6, N3, acc);
+        else if (nfull * kZTile < L6)
+            gdots_tile<false, TA, TZ, NF, true, C>(a, tile * kZTile, Z + (tile * zP + j0) * (long long)kZTile, lo,
+                                                   nj, tile * kZTile + lo, L6, N3, acc);
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int u = 0; u < C; ++u) {
             const double sum = wave_sum(acc[f][u]);
             if (lane == 0 && u < nj) part[(long long)(f * ld + j0 + u) * gridDim.x + blockIdx.x] = sum;
         }
@@ -1736,6 +1816,83 @@ __global__ __launch_bounds__(kThreads) void k_recombine(const T* __restrict__ xi
             T v = xi[i];
             for (int j = 0; j < p; ++j) v += dj[j] * Z[zix(i, j, zP)];
             eps[i] = v;
+        }
+    }
+}
+
+// The same recombination with the columns split over the waves of a block:
+// block b takes the TB basis tiles TB b .. TB b + TB - 1 (kZTile elements,
+// four per lane, FP32); wave w sums columns C w .. C w + C - 1 (then the same
+// plus 16 C, ...) of them, issuing its C * TB loads together, and wave 0 adds
+// the other waves' partial sums from LDS and xi.  The block's waves read the
+// group's slices of all columns, one contiguous region, together: a wave
+// streaming all columns of its own tile reaches ~10 % less of the HBM rate.
+// The grid covers whole groups only (the host takes the remaining tiles).
+#ifndef RPM_RS_CPW
+#define RPM_RS_CPW 2
+#endif
+#ifndef RPM_RS_TPB
+#define RPM_RS_TPB 4
+#endif
+constexpr int kRsWaves = 16;
+template <typename T, int C = RPM_RS_CPW, int TB = RPM_RS_TPB>
+__global__ __launch_bounds__(64 * kRsWaves) void k_recombine_split(const T* __restrict__ xi, const T* __restrict__ Z,
+                                                                   int p, int zP, const double* __restrict__ dco,
+                                                                   T* __restrict__ eps, const int* __restrict__ done)
+{
+    static_assert(sizeof(T) == 4 && kZTile == 64 * 4, "FP32 tiles of four elements per lane");
+    if (done && *done) return;
+    using V = typename Vec4<T>::type;
+    constexpr int CS = kRsWaves * C;  // columns per round of the waves
+    __shared__ T dj[kMaxP + CS];
+    __shared__ V prt[kRsWaves - 1][TB][64];
+    for (int j = threadIdx.x; j < kMaxP + CS; j += 64 * kRsWaves) dj[j] = j < p ? (T)dco[j] : T(0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    V acc[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+        const long long e = ((long long)blockIdx.x * TB + t) * kZTile + lane * 4;
+        acc[t] = w == 0 ? *reinterpret_cast<const V*>(xi + e) : V{T(0), T(0), T(0), T(0)};
+    }
+    const T* zt0 = Z + zix((long long)blockIdx.x * TB * kZTile, 0, zP) + lane * 4;
+    for (int g = C * w; g < p; g += CS) {
+        V z[TB][C];
+#pragma unroll
+        for (int t = 0; t < TB; ++t)
+#pragma unroll
+            for (int u = 0; u < C; ++u)
+                z[t][u] = nt_load(reinterpret_cast<const V*>(zt0 + (long long)t * zP * kZTile +
+                                                             (long long)min(g + u, p - 1) * kZTile));
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            T* a = reinterpret_cast<T*>(&acc[t]);
+#pragma unroll
+            for (int u = 0; u < C; ++u) {
+                const T* zs = reinterpret_cast<const T*>(&z[t][u]);
+                const T c = dj[g + u];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] += c * zs[q];
+            }
+        }
+    }
+    if (w > 0)
+#pragma unroll
+        for (int t = 0; t < TB; ++t) prt[w - 1][t][lane] = acc[t];
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            T* a = reinterpret_cast<T*>(&acc[t]);
+#pragma unroll
+            for (int k = 0; k < kRsWaves - 1; ++k) {
+                const T* b = reinterpret_cast<const T*>(&prt[k][t][lane]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a[q] += b[q];
+            }
+            const long long e = ((long long)blockIdx.x * TB + t) * kZTile + lane * 4;
+            *reinterpret_cast<V*>(eps + e) = acc[t];
         }
     }
 }

@@ -74,6 +74,17 @@ constexpr bool kXInPlace = RPM_X_INPLACE != 0;  // in-place x transforms
 // RPM recombination inside the x-forward pass (in-place 128-point x
 // transforms, not the polarization map)
 constexpr bool kFuseRecombine = RPM_FUSE_RECOMBINE != 0;
+#ifndef RPM_SPLIT_RECOMBINE
+#define RPM_SPLIT_RECOMBINE 1
+#endif
+// FP32 recombination as its own pass with the basis columns split over the
+// waves of a block (k_recombine_split) instead of inside the x-forward pass
+constexpr bool kSplitRecombine = RPM_SPLIT_RECOMBINE != 0;
+#ifndef RPM_SPLIT_DOTS
+#define RPM_SPLIT_DOTS 1
+#endif
+// FP32 per-step basis products with two columns per wave (k_gdots_split)
+constexpr bool kSplitDots = RPM_SPLIT_DOTS != 0;
 constexpr int kGipBlocks = RPM_GIP_BLOCKS;      // persistent grid with in-place transforms
 constexpr int kGPipeBlocks = RPM_GPIPE_BLOCKS;  // its persistent grid
 #ifndef RPM_X_NT
@@ -500,7 +511,11 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     constexpr int XT = x_threads<T>();
     const double cf = (double)g.ncomp / 6.0;  // spectral components carried forward, over 6
     const double bx = fieldB + (use_ref ? 0.0 : (double)g.N) + cf * specB;
-    const bool fuse = eps_store && kFuseRecombine && sh.xip && vec && !pol;
+    // FP32 with whole basis tiles: the split-column streaming pass plus the
+    // plain x pass beat the fused pass (its one resident round of blocks
+    // cannot overlap their transforms with the stream)
+    const bool split = sizeof(T) == 4 && kSplitRecombine && (6 * g.N) % kZTile == 0;
+    const bool fuse = eps_store && kFuseRecombine && sh.xip && vec && !pol && !split;
     if (fuse) {
         // eps = xin + Z d recombined inside the x pass (stored for the x-inverse)
         c.mark_begin(RPM_K_XFWD, ev);
@@ -516,7 +531,24 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
         const int VL = 16 / (int)sizeof(T);
         const int gb = (int)((nel / VL + kThreads - 1) / kThreads) + 1;
         c.mark_begin(RPM_K_RECOMBINE, ev);
-        k_recombine<T><<<gb, kThreads, 0, c.s>>>(xin, c.Zb(), p_corr, c.pmax, c.st->d, eps_store, nel, done);
+        if constexpr (sizeof(T) == 4) {
+            if (split && p_corr > 0) {
+                // whole groups of RPM_RS_TPB tiles, then the remaining tiles
+                // (addressed from their first tile) one run per thread
+                const long long ngrp = nel / kZTile / RPM_RS_TPB;
+                const long long off = ngrp * RPM_RS_TPB * kZTile;
+                if (ngrp > 0)
+                    k_recombine_split<T><<<(int)ngrp, 64 * kRsWaves, 0, c.s>>>(xin, c.Zb(), p_corr, c.pmax, c.st->d,
+                                                                               eps_store, done);
+                if (off < nel)
+                    k_recombine<T><<<(int)((nel - off) / VL + kThreads - 1) / kThreads + 1, kThreads, 0, c.s>>>(
+                        xin + off, c.Zb() + off * c.pmax, p_corr, c.pmax, c.st->d, eps_store + off, nel - off, done);
+            } else {
+                k_recombine<T><<<gb, kThreads, 0, c.s>>>(xin, c.Zb(), p_corr, c.pmax, c.st->d, eps_store, nel, done);
+            }
+        } else {
+            k_recombine<T><<<gb, kThreads, 0, c.s>>>(xin, c.Zb(), p_corr, c.pmax, c.st->d, eps_store, nel, done);
+        }
         c.mark_end(RPM_K_RECOMBINE, ev, fieldB * (2 + p_corr));
         xin = eps_store;
     }
@@ -637,8 +669,15 @@ void project(Ctx<T>& c, const T* xi, const T* eps, int p, bool direct)
     if (direct)
         launch_gdots<T, T, 2, 0>(c.s, c.sh.Gq, Fields<T>{{xi, eps}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(),
                                  c.L.ld);
-    else
+    else if constexpr (sizeof(T) == 4) {
+        if (kSplitDots && p <= 16 * RPM_GS_CPW)
+            k_gdots_split<T, T, 1, 0><<<c.sh.Gq, 64 * ((p + RPM_GS_CPW - 1) / RPM_GS_CPW), 0, c.s>>>(
+                Fields<T>{{xi}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+        else
+            launch_gdots<T, T, 1, 0>(c.s, c.sh.Gq, Fields<T>{{xi}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+    } else {
         launch_gdots<T, T, 1, 0>(c.s, c.sh.Gq, Fields<T>{{xi}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+    }
     c.mark_end(RPM_K_PROJECT, ev, 6.0 * (double)c.sh.g.N * sizeof(T) * ((direct ? 2 : 1) + p));
 }
 

@@ -120,10 +120,11 @@ def test_rpm_random_3d_fp64(B, shape):
     assert np.abs(eps - ref["eps"]).max() <= 1e-10 * np.abs(ref["eps"]).max()
 
 
-def test_rpm_random_3d_fp32_fused_x_pass(B):
-    """FP32 fields on a grid whose x pass recombines eps = xi + Z d on the way
-    in (nx = 128): the certified solution matches the oracle's (FP32 bar: 1e-4
-    relative in the field)."""
+def test_rpm_random_3d_fp32_x128(B):
+    """FP32 fields on a grid with 128-point in-place x transforms and x-pass
+    tiles of 12 rows (the recombination eps = xi + Z d as its own pass with
+    the columns split over the waves): the certified solution matches the
+    oracle's (FP32 bar: 1e-4 relative in the field)."""
     ph = M.random_phases((6, 12, 128), 2, seed=102)
     phases = [(1.0, 0.3), (100.0, 0.3)]
     E = np.array([0.0, 0.0, 0.01, 0.0, 0.003, 0.0])
@@ -132,6 +133,32 @@ def test_rpm_random_3d_fp32_fused_x_pass(B):
     g = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(50.5, 0.3), E,
                     B.make_options(scheme="rpm", precision="fp32", tol=1e-7, n_max=6, p_max=16, max_iter=3000))
     assert ref["status"] == "converged" and g["status"] == "RPM_OK" and g["basis_dim"] > 0
+    assert g["residual_fp64"] <= 1e-7
+    eps = g["eps"].cpu().numpy().astype(np.float64)
+    assert np.abs(eps - ref["eps"]).max() <= 1e-4 * np.abs(ref["eps"]).max()
+
+
+@pytest.mark.parametrize("shape,p_max", [((3, 32, 128), 16), ((3, 32, 128), 40), ((3, 6, 128), 16),
+                                         ((6, 12, 18), 16)],
+                         ids=["3x32x128-p16", "3x32x128-p40", "3x6x128-p16", "6x12x18-p16"])
+def test_rpm_random_3d_fp32_recombination(B, shape, p_max):
+    """FP32 RPM through the recombination and projection passes with the basis
+    columns split over the waves of a block (6N a multiple of the basis tile:
+    whole groups of four tiles, and 54 tiles, two past the last group; p_max
+    40 gives the waves a second round of columns and takes the projections
+    with eight columns per wave) and through the one-run-per-thread passes
+    (6 x 12 x 18, a partial last tile).  The certified solution matches the
+    oracle's (FP32 bar: 1e-4 relative in the field)."""
+    print(f"fp32 recombination {shape} p_max={p_max}", flush=True)
+    ph = M.random_phases(shape, 2, seed=103)
+    phases = [(1.0, 0.3), (100.0, 0.3)]
+    E = np.array([0.01, 0.0, 0.0, 0.0, 0.0, 0.004])
+    l0 = O.lame(50.5, 0.3)
+    ref = O.solve(ph, O.lame_table(phases), l0, E, scheme="rpm", tol=1e-10, n_max=4, p_max=p_max, max_iter=3000)
+    g = B.fft_solve(dev(ph), gpu_lame(B, phases), B.lame_from_young(50.5, 0.3), E,
+                    B.make_options(scheme="rpm", precision="fp32", tol=1e-7, n_max=4, p_max=p_max, max_iter=3000))
+    assert ref["status"] == "converged" and g["status"] == "RPM_OK"
+    assert g["basis_dim"] > (32 if p_max > 32 else 0)
     assert g["residual_fp64"] <= 1e-7
     eps = g["eps"].cpu().numpy().astype(np.float64)
     assert np.abs(eps - ref["eps"]).max() <= 1e-4 * np.abs(ref["eps"]).max()
