@@ -83,7 +83,7 @@ constexpr bool kSplitRecombine = RPM_SPLIT_RECOMBINE != 0;
 #ifndef RPM_SPLIT_DOTS
 #define RPM_SPLIT_DOTS 1
 #endif
-// FP32 per-step basis products with two columns per wave (k_gdots_split)
+// FP32 per-step basis products with two or four columns per wave (k_gdots_split)
 constexpr bool kSplitDots = RPM_SPLIT_DOTS != 0;
 constexpr int kGipBlocks = RPM_GIP_BLOCKS;      // persistent grid with in-place transforms
 constexpr int kGPipeBlocks = RPM_GPIPE_BLOCKS;  // its persistent grid
@@ -670,9 +670,12 @@ void project(Ctx<T>& c, const T* xi, const T* eps, int p, bool direct)
         launch_gdots<T, T, 2, 0>(c.s, c.sh.Gq, Fields<T>{{xi, eps}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(),
                                  c.L.ld);
     else if constexpr (sizeof(T) == 4) {
-        if (kSplitDots && p <= 16 * RPM_GS_CPW)
-            k_gdots_split<T, T, 1, 0><<<c.sh.Gq, 64 * ((p + RPM_GS_CPW - 1) / RPM_GS_CPW), 0, c.s>>>(
-                Fields<T>{{xi}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
+        if (kSplitDots && p <= 32)
+            k_gdots_split<T, T, 1, 0, 2, 8><<<c.sh.Gq, 64 * ((p + 1) / 2), 0, c.s>>>(Fields<T>{{xi}}, c.Zb(), p, c.pmax,
+                                                                                    c.sh.g.N, c.pdots(), c.L.ld);
+        else if (kSplitDots && p <= 64)
+            k_gdots_split<T, T, 1, 0, 4, 4><<<c.sh.Gq, 64 * ((p + 3) / 4), 0, c.s>>>(Fields<T>{{xi}}, c.Zb(), p, c.pmax,
+                                                                                    c.sh.g.N, c.pdots(), c.L.ld);
         else
             launch_gdots<T, T, 1, 0>(c.s, c.sh.Gq, Fields<T>{{xi}}, c.Zb(), p, c.pmax, c.sh.g.N, c.pdots(), c.L.ld);
     } else {

@@ -145,8 +145,8 @@ def test_rpm_random_3d_fp32_recombination(B, shape, p_max):
     """FP32 RPM through the recombination and projection passes with the basis
     columns split over the waves of a block (6N a multiple of the basis tile:
     whole groups of four tiles, and 54 tiles, two past the last group; p_max
-    40 gives the waves a second round of columns and takes the projections
-    with eight columns per wave) and through the one-run-per-thread passes
+    40 gives the recombination's waves a second round of columns and the
+    projections four columns per wave) and through the one-run-per-thread passes
     (6 x 12 x 18, a partial last tile).  The certified solution matches the
     oracle's (FP32 bar: 1e-4 relative in the field)."""
     print(f"fp32 recombination {shape} p_max={p_max}", flush=True)
