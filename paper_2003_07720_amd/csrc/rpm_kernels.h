@@ -5,15 +5,19 @@
 // spectrum is transposed as it goes, so that every pass reads or writes whole
 // contiguous rows and the other side in 128-byte (or longer) segments:
 //
-//   xfwd   strain tile -> eps = xi_prev + Z d (RPM recombination), sigma =
-//          C(x):eps in registers, real-to-complex FFT along x (two components
-//          packed per complex FFT), spectrum written as S1[c][kx][z][y]
+//   xfwd   strain tile -> sigma = C(x):eps in registers, real-to-complex
+//          FFT along x (two components packed per complex FFT), spectrum
+//          written as S1[c][kx][z][y]
 //   yfwd   S1 rows along y -> FFT -> S2[c][ky][kx][z]
 //   gamma  S2 rows along z -> FFT -> per frequency t = Gamma0(k):sigma_hat,
 //          equilibrium-error partial sums, <sigma> -> inverse FFT in place
 //   yinv   S2 -> inverse FFT along y -> S1
-//   xinv   S1 -> complex-to-real inverse FFT along x -> xi = eps - t, and the
-//          projections Z^T xi, Z^T eps (FP64 accumulation)
+//   xinv   S1 -> complex-to-real inverse FFT along x -> xi = eps - t
+//
+// and, in an RPM iteration, two streams over the basis Z: the recombination
+// eps = xi_prev + Z d before the map (k_recombine_split for FP32 fields; for
+// FP64 fields on 128-point rows inside xfwd, else k_recombine) and the
+// projections Z^T xi after it (k_gdots_split / k_gdots, FP64 accumulation).
 //
 // In 2-D (nz == 1) the y passes are skipped and gamma runs along y on S1.
 // The k = 0 term of t is N(<eps> - E), so xi = eps - F^-1[Gamma sigma_hat]
@@ -42,7 +46,8 @@ __device__ __forceinline__ double2 nt_load(const double2* p)
 // waves per SIMD the compiler budgets registers for: the in-place gamma pass
 // (five resident blocks per CU), and the x pass that recombines eps = xi + Z d
 // on the way in (four; with 8 basis columns in flight per lane it needs ~114
-// VGPRs, and 16 columns spill at four waves and drop to three)
+// VGPRs, and 16 columns spill at four waves and drop to three); RC_GROUP is
+// the basis columns in flight per lane there
 #ifndef RPM_GIP_WPE
 #define RPM_GIP_WPE 5
 #endif
