@@ -41,7 +41,7 @@ CLASS_SYMBOLS = {
     "yinv": r"rpm::k_ypipe<{T}, 1, \d+(, (true|false))?>|rpm::k_yinv<{T}>",
     "xinv": r"rpm::k_xinv<{T}, false(, \d+)?(, (true|false))?>",
     "project": r"rpm::k_gdots(_split)?<{T}, {T}, [12], 0(, \d+, \d+)?>",
-    "recombine": r"rpm::k_recombine(_split)?<{T}>",
+    "recombine": r"rpm::k_recombine(_split)?<{T}(, \d+, \d+)?>",
 }
 
 
