@@ -1126,9 +1126,10 @@ __global__ __launch_bounds__(512) void k_gdots(Fields<TA> a, const TZ* __restric
 // (the block has ceil(p / C) <= 16 waves) and streams their slices of TB
 // consecutive tiles per round (C * TB loads issued together), so the block's
 // waves read each group of tiles' slices of all columns, one contiguous
-// region, together (C = 2, TB = 8 for p <= 32 and C = 4, TB = 4 for p <= 64
-// stream 2-5 % faster than eight columns per wave).  Same partial-sum layout
-// as k_gdots.
+// region, together (FP32: C = 2, TB = 8 for p <= 32 and C = 4, TB = 4 for
+// p <= 64 stream 2-5 % faster than eight columns per wave; FP64, two 16-byte
+// loads per column slice: TB = 1, 6-9 % faster).  Same partial-sum layout as
+// k_gdots.
 template <typename TA, typename TZ, int NF, int SITE, int C, int TB>
 __global__ __launch_bounds__(1024) void k_gdots_split(Fields<TA> a, const TZ* __restrict__ Z, int p, int zP,
                                                       long long N, double* __restrict__ part, int ld)
