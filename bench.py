@@ -711,8 +711,10 @@ def disk32_row(B, M, torch):
                 status=st, seconds=round(el, 4), iterations=[x["iterations"] for x in stats],
                 jvps=sum(x["jvps"] for x in stats), C11=C[0][0], C33=C[2][2])
         # the uneven grids of the batched benchmark family: the tile autotuner's
-        # shape against the default, per map application (FP32)
-        for n in (48, 96):
+        # shape against the default, per map application (FP32); at 128^3 also
+        # the y transforms held in registers (DPP exchanges), which the tuner
+        # times as a candidate
+        for n in (48, 96, 128):
             cell = M.random_phases((n, n, n), 2, seed=40 + n)
             ph = torch.from_numpy(cell).to("cuda")
             lt = np.array([B.lame_from_young(*p) for p in [(1.0, 0.3), (50.0, 0.3)]])
@@ -723,7 +725,8 @@ def disk32_row(B, M, torch):
             t = B.autotune(ph, lt, l0, o, reps=20, workspace=ws)
             tune_s = time.perf_counter() - t0
             ms = {}
-            for name, tn in (("default", None), ("tuned", t["tuning"])):
+            shapes = [("default", None), ("tuned", t["tuning"])] + ([("y_regs", dict(y_regs=1))] if n == 128 else [])
+            for name, tn in shapes:
                 # 200 RPM steps each (a tolerance no step reaches), basis up to 32
                 oo = B.make_options(scheme="rpm", precision="fp32", p_max=32, tol=1e-15, max_iter=200, refine=0,
                                     check_every=32, tuning=tn)
@@ -731,8 +734,7 @@ def disk32_row(B, M, torch):
                 ms[name] = round(el / (r["iterations"] + r["jvps"]) * 1e3, 4)
             out[f"autotune_{n}cube_fp32"] = dict(tuning=t["tuning"].as_dict(), tuner_ms_per_map=round(t["ms"], 4),
                                                  candidates=t["candidates"], tune_seconds=round(tune_s, 3),
-                                                 ms_per_map_solve_default=ms["default"],
-                                                 ms_per_map_solve_tuned=ms["tuned"])
+                                                 **{f"ms_per_map_solve_{k}": v for k, v in ms.items()})
     # the batched family: seeded two-phase cells of uneven grids, the six unit
     # load cases each (FP32, FP64 refinement, tol 1e-6), one worker against four
     # and eight concurrent workers (a stream each), launch shapes tuned per grid

@@ -61,18 +61,25 @@ extern "C" {
 /* Launch shape of the y and gamma pencil passes of one grid and precision
  * (the batched, uneven-grid workloads of the paper's benchmark families run
  * many grids; the best shape differs between them).  A field of 0 keeps the
- * library's default.  None changes a result: every element is transformed
- * with the same arithmetic; only the grouping of the per-block error partial
- * sums follows gamma_blocks.
+ * library's default.  The shapes do not change a result: every element is
+ * transformed with the same arithmetic; only the grouping of the per-block
+ * error partial sums follows gamma_blocks.  y_regs changes the factorisation
+ * of the y transforms, so their rounding.
  *   y_cols        z positions per y-pass tile: a divisor of nz, at most
  *                 128 / (2 sizeof(real)) and 8 x 256 / ny; other values make
  *                 the calls that use the tuning return RPM_E_INVALID
  *   y_blocks      workgroups of the persistent y passes (>= 1)
- *   gamma_blocks  workgroups of the persistent gamma pass (>= 1)          */
+ *   gamma_blocks  workgroups of the persistent gamma pass (>= 1)
+ *   y_regs        1: the 128-point y transforms held in registers, a row per
+ *                 16 lanes, exchanged across lanes by DPP moves, without LDS
+ *                 (FP32 fields, ny = 128, 3-D, nz a multiple of 16, y_cols
+ *                 0 or 16, y_blocks 0; elsewhere RPM_E_INVALID); 0: the LDS
+ *                 passes                                                   */
 typedef struct rpm_tuning_s {
     int32_t y_cols;
     int32_t y_blocks;
     int32_t gamma_blocks;
+    int32_t y_regs;
 } rpm_tuning;
 
 typedef enum {

@@ -37,10 +37,11 @@ class RpmProblem(ctypes.Structure):
 
 
 class RpmTuning(ctypes.Structure):
-    _fields_ = [("y_cols", ctypes.c_int32), ("y_blocks", ctypes.c_int32), ("gamma_blocks", ctypes.c_int32)]
+    _fields_ = [("y_cols", ctypes.c_int32), ("y_blocks", ctypes.c_int32), ("gamma_blocks", ctypes.c_int32),
+                ("y_regs", ctypes.c_int32)]
 
     def as_dict(self):
-        return dict(y_cols=self.y_cols, y_blocks=self.y_blocks, gamma_blocks=self.gamma_blocks)
+        return dict(y_cols=self.y_cols, y_blocks=self.y_blocks, gamma_blocks=self.gamma_blocks, y_regs=self.y_regs)
 
 
 class RpmOptions(ctypes.Structure):

@@ -24,6 +24,8 @@
 // + (E - <eps>), which is exactly the paper's update with xi_hat(0) = N E.
 #pragma once
 
+#include <type_traits>
+
 #include "rpm_device.h"
 
 namespace rpm {
@@ -443,6 +445,110 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof
                 dst[e] = R[r * ss + lpad(y)];
             }
         }
+    }
+}
+
+// Cross-lane exchange within rows of 16 lanes through the data-parallel
+// primitives (DPP) of the vector ALU: the value of lane l ^ H (H = 1, 2, 4, 8).
+// H = 4 takes two moves (lanes 4..7 of each 8 from the right, 0..3 from the
+// left, selected by bank masks).
+template <int H>
+__device__ __forceinline__ float lane_xor(float v)
+{
+    const int i = __float_as_int(v);
+    int r;
+    if constexpr (H == 1) r = __builtin_amdgcn_update_dpp(i, i, 0xB1, 0xF, 0xF, false);        // quad_perm 1,0,3,2
+    else if constexpr (H == 2) r = __builtin_amdgcn_update_dpp(i, i, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    else if constexpr (H == 8) r = __builtin_amdgcn_update_dpp(i, i, 0x128, 0xF, 0xF, false);  // row_ror 8
+    else {
+        r = __builtin_amdgcn_update_dpp(i, i, 0x104, 0xF, 0x5, false);  // row_shl 4 into banks 0, 2
+        r = __builtin_amdgcn_update_dpp(r, i, 0x114, 0xF, 0xA, false);  // row_shr 4 into banks 1, 3
+    }
+    return __int_as_float(r);
+}
+
+// y passes with the 128-point transforms in registers (FP32, ny = 128, tiles
+// of 16 z rows, nz % 16 == 0): wave w of a block takes rows 4w .. 4w+3 of the
+// tile, one row per 16-lane group; lane j of a group holds elements 8j .. 8j+7
+// of its row.  With n = 8j + m and k = k2 + 16 k1: a 16-point DFT over j
+// across the group's lanes (four radix-2 stages, partners exchanged by DPP,
+// output k2 at lane bitrev(k2)), twiddles w128^(m k2), and an 8-point DFT over
+// m in registers give X[k2 + 16 k1] in register k1 — for each k1 the group
+// holds 16 consecutive outputs.  No LDS and no barriers: rows along y are read
+// (forward) or written (inverse) as 64-byte runs per lane or 128-byte runs per
+// group, the transposed side S2[c][ky][kx][z] as 32-byte runs of the four rows
+// of a wave (the block's four waves complete each 128-byte line).
+template <int D>
+__global__ __launch_bounds__(kThreads) void k_ywave(const cx<float>* __restrict__ Sin, cx<float>* __restrict__ Sout,
+                                                    Geo g, const cx<float>* __restrict__ twy,
+                                                    const int* __restrict__ done)
+{
+    if (done && *done) return;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15;
+    const int r = 4 * (threadIdx.x >> 6) + (lane >> 4);  // row of the tile
+    const int nzt = g.nz / 16;
+    int b = blockIdx.x;
+    const int zt = b % nzt;
+    b /= nzt;
+    const int kx = b % g.nh;
+    const int c = b / g.nh;
+    const int z = zt * 16 + r;
+    const long long cb = (long long)c * g.nspec;
+    cx<float> v[8];
+    if constexpr (D < 0) {
+        // row (c, kx, z) of S1, elements 8j .. 8j+7
+        const float4* src = reinterpret_cast<const float4*>(Sin + cb + ((long long)kx * g.nz + z) * 128 + 8 * j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t = src[q];
+            v[2 * q] = cx<float>{t.x, t.y};
+            v[2 * q + 1] = cx<float>{t.z, t.w};
+        }
+    } else {
+        // S2[c][ky][kx][z] for ky = 8j + m
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = Sin[cb + ((long long)(8 * j + m) * g.nh + kx) * g.nz + z];
+    }
+    // 16-point DIF over j: span h, lower lanes a + b, upper (a - b) w_2h^(j mod h)
+    auto stage = [&](auto hc) {
+        constexpr int H = decltype(hc)::value;
+        const bool up = (j & H) != 0;
+        const float sg = up ? -1.f : 1.f;
+        cx<float> w = {1.f, 0.f};
+        if (H > 1 && up) {
+            w = twy[(j & (H - 1)) * (64 / H)];  // w_2h^e = w_128^(64 e / h)
+            if (D > 0) w.y = -w.y;
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const float px = lane_xor<H>(v[m].x), py = lane_xor<H>(v[m].y);
+            cx<float> t = {px + sg * v[m].x, py + sg * v[m].y};
+            if constexpr (H > 1) t = cmul(t, w);
+            v[m] = t;
+        }
+    };
+    stage(std::integral_constant<int, 8>{});
+    stage(std::integral_constant<int, 4>{});
+    stage(std::integral_constant<int, 2>{});
+    stage(std::integral_constant<int, 1>{});
+    const int k2 = (int)(__builtin_bitreverse32((unsigned)j) >> 28);
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+        cx<float> w = twy[(m * k2) & 127];
+        if (D > 0) w.y = -w.y;
+        v[m] = cmul(v[m], w);
+    }
+    dftR<float, 8, D>(v);
+    if constexpr (D < 0) {
+        // X[ky], ky = k2 + 16 k1, to S2[c][ky][kx][z]
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1)
+            Sout[cb + ((long long)(k2 + 16 * k1) * g.nh + kx) * g.nz + z] = v[k1];
+    } else {
+        cx<float>* dst = Sout + cb + ((long long)kx * g.nz + z) * 128;
+#pragma unroll
+        for (int k1 = 0; k1 < 8; ++k1) dst[k2 + 16 * k1] = v[k1];
     }
 }
 

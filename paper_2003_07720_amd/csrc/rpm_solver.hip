@@ -154,6 +154,7 @@ struct Shapes {
     int Yb;                           // workgroups of the persistent y passes
     bool ok;
     bool tune_ok;                     // the launch-shape overrides (rpm_tuning) apply to this grid
+    bool yregs;                       // y transforms in registers (k_ywave)
 };
 
 template <typename T>
@@ -233,6 +234,9 @@ Shapes<T> make_shapes(const int32_t n[3], int ncomp, const rpm_tuning* tn = null
     s.G3 = s.gpipe ? std::min(s.Gt, s.gip ? kGipBlocks : kGPipeBlocks) : s.Gt;  // gamma blocks (one error partial each)
     s.Yb = s.yip ? kYipBlocks : kYPipeBlocks;
     if (tn && tn->y_blocks > 0) s.Yb = tn->y_blocks;
+    s.yregs = tn && tn->y_regs > 0;
+    if (s.yregs && !(sizeof(T) == 4 && !g.two_d && g.ny == 128 && g.tz == 16 && tn->y_blocks == 0))
+        s.tune_ok = false;
     if (tn && tn->gamma_blocks > 0 && s.gpipe) s.G3 = std::min(s.Gt, tn->gamma_blocks);
     s.Gg = (int)((g.N + kChunk - 1) / kChunk);
     s.Gp = (int)((6 * g.N + kVecBlock - 1) / kVecBlock);
@@ -488,6 +492,14 @@ struct Ctx {
     }
 };
 
+// y passes with register-resident transforms (rpm_tuning.y_regs; FP32 only)
+template <typename T, int D>
+void launch_ywave(hipStream_t s, int tiles, const cx<T>* Sin, cx<T>* Sout, const Geo& g, const cx<T>* tw,
+                  const int* done)
+{
+    if constexpr (sizeof(T) == 4) k_ywave<D><<<tiles, kThreads, 0, s>>>(Sin, Sout, g, tw, done);
+}
+
 // One application of the fixed-point map on field xin (optionally corrected
 // by Z d), leaving partial sums for the error and the projections.
 template <typename T>
@@ -579,7 +591,9 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     if (!g.two_d) {
         const int tiles = pol ? sh.Gyf : sh.Gy;
         c.mark_begin(RPM_K_YFWD, ev);
-        if (kYPipe && sh.yip)
+        if (sh.yregs)
+            launch_ywave<T, -1>(c.s, tiles, S1, S2, g, c.twy(), done);
+        else if (kYPipe && sh.yip)
             k_ypipe<T, -1, 8, true><<<std::min(tiles, sh.Yb), kThreads, sh.lds_y, c.s>>>(S1, S2, g, sh.py,
                                                                                              c.twy(), tiles, done);
         else if (kYPipe && g.tz * g.ny <= 8 * kThreads)
@@ -607,7 +621,9 @@ void run_F(Ctx<T>& c, const T* xin, int p_corr, T* eps_store, const T* eps_for_i
     c.mark_end(RPM_K_GAMMA, ev, ((pol ? cf : 1.0) + 1.0) * specB);
     if (!g.two_d) {
         c.mark_begin(RPM_K_YINV, ev);
-        if (kYPipe && sh.yip)
+        if (sh.yregs)
+            launch_ywave<T, 1>(c.s, sh.Gy, S2, S1, g, c.twy(), done);
+        else if (kYPipe && sh.yip)
             k_ypipe<T, 1, 8, true><<<std::min(sh.Gy, sh.Yb), kThreads, sh.lds_y, c.s>>>(S2, S1, g, sh.py,
                                                                                             c.twy(), sh.Gy, done);
         else if (kYPipe && g.tz * g.ny <= 8 * kThreads)
@@ -1396,7 +1412,8 @@ rpm_status validate(const rpm_problem* pr, const rpm_options* o)
     if (o->batch_cases < 0 || o->batch_cases > 2) return RPM_E_INVALID;
     if (o->graph != 0 && o->graph != 1) return RPM_E_INVALID;
     if (o->profile_every < 0) return RPM_E_INVALID;
-    if (o->tuning && (o->tuning->y_cols < 0 || o->tuning->y_blocks < 0 || o->tuning->gamma_blocks < 0))
+    if (o->tuning && (o->tuning->y_cols < 0 || o->tuning->y_blocks < 0 || o->tuning->gamma_blocks < 0 ||
+                      o->tuning->y_regs < 0 || o->tuning->y_regs > 1))
         return RPM_E_INVALID;
     if (o->map == RPM_MAP_POLARIZATION &&
         (!finite(o->alpha) || !(o->alpha > 0.0) || !finite(o->beta) || !(o->beta > 0.0)))
@@ -1474,7 +1491,7 @@ rpm_status apply_typed(const rpm_problem* pr, const double E[6], const rpm_optio
 }
 
 // Tile autotuner: times the map under candidate launch shapes (coordinate
-// search over y_cols, y_blocks, gamma_blocks; 0 = default first).
+// search over y_regs, y_cols, y_blocks, gamma_blocks; 0 = default first).
 template <typename T>
 rpm_status tune_typed(const rpm_problem* pr, const rpm_options* o, int reps, rpm_tuning* best, double* best_ms,
                       int32_t* ncand, void* ws, size_t ws_bytes, void* stream)
@@ -1517,9 +1534,22 @@ rpm_status tune_typed(const rpm_problem* pr, const rpm_options* o, int reps, rpm
         ++count;
         return hip_ok ? (double)ms / reps : -1.0;
     };
-    rpm_tuning cur{0, 0, 0};
+    rpm_tuning cur{0, 0, 0, 0};
     double cur_ms = time_shape(cur);
     const Geo& g = base.g;
+    // the y transforms in registers, where they apply
+    {
+        rpm_tuning tn = cur;
+        tn.y_regs = 1;
+        const Shapes<T> sh = make_shapes<T>(pr->n, spectral_comps(&ob), &tn);
+        if (sh.ok && sh.tune_ok && hip_ok) {
+            const double ms = time_shape(tn);
+            if (ms >= 0.0 && ms < cur_ms) {
+                cur = tn;
+                cur_ms = ms;
+            }
+        }
+    }
     // y_cols: admissible divisors of nz, largest first (3-D only)
     if (!g.two_d) {
         int tried = 0;

@@ -102,7 +102,7 @@ def _raw_problem(B, n=(8, 8, 8), lame=((1.0, 1.0),), lame0=(1.0, 1.0)):
 
 @pytest.mark.parametrize("case", ["tol", "nan_E", "pmax", "mu0", "neg_mu", "scheme", "check", "size", "nphase",
                                   "workspace", "kappa", "replay", "map", "alpha", "classes", "every", "tune_neg",
-                                  "tune_cols", "tune_wide"])
+                                  "tune_cols", "tune_wide", "tune_regs_neg", "tune_regs_2", "tune_regs_grid"])
 def test_solve_rejects_bad_arguments_before_device_work(B, case):
     lib = B._lib
     o = B.make_options()
@@ -156,6 +156,15 @@ def test_solve_rejects_bad_arguments_before_device_work(B, case):
     elif case == "tune_wide":  # more z positions per y tile than the pass holds
         tn = B.RpmTuning(64, 0, 0)
         pr = _raw_problem(B, n=(64, 64, 64))
+        o.tuning = ctypes.pointer(tn)
+    elif case == "tune_regs_neg":
+        tn = B.RpmTuning(0, 0, 0, -1)
+        o.tuning = ctypes.pointer(tn)
+    elif case == "tune_regs_2":
+        tn = B.RpmTuning(0, 0, 0, 2)
+        o.tuning = ctypes.pointer(tn)
+    elif case == "tune_regs_grid":  # register y transforms need ny = 128 (here 8)
+        tn = B.RpmTuning(0, 0, 0, 1)
         o.tuning = ctypes.pointer(tn)
     rc = lib.rpm_fft_solve(ctypes.byref(pr), E, ctypes.byref(o), None, None, None, None, None, ws, wsb, None)
     assert rc == expect, (case, rc)

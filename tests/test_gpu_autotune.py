@@ -6,7 +6,9 @@ with the same arithmetic, so fields must come out bitwise equal to the
 default shape's, on the uneven grids of the benchmark families (48^3, a
 mixed 32 x 48 x 64 box) as on a power-of-two one; only the equilibrium
 error, a sum of per-block partials whose grouping follows the gamma grid,
-may differ in its last bits.
+may differ in its last bits.  The y transforms held in registers (y_regs)
+factor the transform differently, so they are compared with the oracle and
+with the default passes to FP32 rounding instead.
 """
 import numpy as np
 import pytest
@@ -84,6 +86,29 @@ def test_explicit_shapes_apply_the_same_map(B, tuning):
     assert torch.equal(xa, xb)
     assert abs(ea - eb) <= 1e-6 * ea
     np.testing.assert_array_equal(sa, sb)
+
+
+@pytest.mark.parametrize("shape", [(16, 128, 8), (32, 128, 6)], ids=["16x128x8", "32x128x6"])
+def test_register_y_transforms_match_the_oracle(B, shape):
+    """y_regs = 1 (128-point y transforms in registers, rows exchanged across
+    lanes by DPP moves) applies the map of the oracle to the FP32 bar, and the
+    LDS passes' result to FP32 rounding."""
+    import torch
+
+    import oracle as O
+
+    print(f"register y transforms {shape}", flush=True)
+    ph, lt, l0 = _cell(B, shape, 9)
+    eps_np = M.random_field(shape, seed=10, scale=0.003) + np.asarray(E)[:, None, None, None]
+    eps = torch.from_numpy(eps_np).float().to("cuda").contiguous()
+    xa, ea, _ = B.fft_apply(ph, lt, l0, E, eps, B.make_options(precision="fp32"))
+    xb, eb, _ = B.fft_apply(ph, lt, l0, E, eps, B.make_options(precision="fp32", tuning=dict(y_regs=1)))
+    scale = float(xa.abs().max())
+    assert float((xa - xb).abs().max()) <= 2e-6 * scale
+    assert abs(ea - eb) <= 1e-5 * ea
+    ref_xi, ref_err, _, _ = O.fmap(ph.cpu().numpy(), O.lame_table(PHASES), O.lame(25.5, 0.3), E, eps_np)
+    assert np.abs(xb.double().cpu().numpy() - ref_xi).max() <= 2e-5 * np.abs(ref_xi).max()
+    assert abs(eb - ref_err) <= 2e-4 * ref_err
 
 
 def test_inapplicable_shape_is_rejected(B):

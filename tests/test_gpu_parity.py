@@ -41,9 +41,10 @@ def gpu_lame(B, phases):
 PHASES3 = [(1.0, 0.3), (7.0, 0.25), (0.2, 0.4)]
 
 # (nz, ny, nx); the 128-point extents take the compile-time transform plans on each axis
+# (ny = 128 with nz a multiple of 16: the FP32 y transforms in registers)
 GRIDS = [(1, 32, 32), (1, 6, 8), (1, 48, 12), (4, 6, 8), (2, 4, 6), (8, 8, 8), (12, 16, 6), (9, 3, 6),
          (3, 9, 27), (16, 16, 16), (6, 96, 4), (32, 12, 48), (1, 16, 128), (1, 128, 6), (128, 4, 6), (4, 128, 6),
-         (6, 4, 128)]
+         (6, 4, 128), (16, 128, 6), (32, 128, 4)]
 
 
 @pytest.mark.parametrize("shape", GRIDS, ids=lambda s: "x".join(map(str, s)))

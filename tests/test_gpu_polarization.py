@@ -32,7 +32,7 @@ def dev(a, dtype=None):
 PHASES = [(1.0, 0.3), (40.0, 0.25), (0.5, 0.4)]
 E6 = np.array([0.01, -0.004, 0.002, 0.003, -0.002, 0.005])
 GRIDS = [(1, 32, 32), (1, 6, 8), (4, 6, 8), (9, 3, 6), (3, 9, 27), (12, 16, 6), (1, 16, 128), (128, 4, 6),
-         (6, 4, 128)]
+         (6, 4, 128), (16, 128, 6)]
 
 
 def _gl(B, phases):
