@@ -468,87 +468,116 @@ __device__ __forceinline__ float lane_xor(float v)
 }
 
 // y passes with the 128-point transforms in registers (FP32, ny = 128, tiles
-// of 16 z rows, nz % 16 == 0): wave w of a block takes rows 4w .. 4w+3 of the
-// tile, one row per 16-lane group; lane j of a group holds elements 8j .. 8j+7
-// of its row.  With n = 8j + m and k = k2 + 16 k1: a 16-point DFT over j
+// of 16 z rows, nz % 16 == 0): a wave takes four rows of a tile at a time, one
+// row per 16-lane group; lane j of a group holds elements 8j .. 8j+7 of its
+// row.  With n = 8j + m and k = k2 + 16 k1: a 16-point DFT over j
 // across the group's lanes (four radix-2 stages, partners exchanged by DPP,
 // output k2 at lane bitrev(k2)), twiddles w128^(m k2), and an 8-point DFT over
 // m in registers give X[k2 + 16 k1] in register k1 — for each k1 the group
 // holds 16 consecutive outputs.  No LDS and no barriers: rows along y are read
 // (forward) or written (inverse) as 64-byte runs per lane or 128-byte runs per
 // group, the transposed side S2[c][ky][kx][z] as 32-byte runs of the four rows
-// of a wave (the block's four waves complete each 128-byte line).
+// of a wave (the four tasks of a tile complete each 128-byte line).  A
+// persistent grid of waves walks the tasks (four rows of a tile each) with the
+// next task's loads in flight.
 template <int D>
 __global__ __launch_bounds__(kThreads) void k_ywave(const cx<float>* __restrict__ Sin, cx<float>* __restrict__ Sout,
-                                                    Geo g, const cx<float>* __restrict__ twy,
+                                                    Geo g, const cx<float>* __restrict__ twy, int ntasks,
                                                     const int* __restrict__ done)
 {
     if (done && *done) return;
     const int lane = threadIdx.x & 63;
     const int j = lane & 15;
-    const int r = 4 * (threadIdx.x >> 6) + (lane >> 4);  // row of the tile
     const int nzt = g.nz / 16;
-    int b = blockIdx.x;
-    const int zt = b % nzt;
-    b /= nzt;
-    const int kx = b % g.nh;
-    const int c = b / g.nh;
-    const int z = zt * 16 + r;
-    const long long cb = (long long)c * g.nspec;
-    cx<float> v[8];
-    if constexpr (D < 0) {
-        // row (c, kx, z) of S1, elements 8j .. 8j+7
-        const float4* src = reinterpret_cast<const float4*>(Sin + cb + ((long long)kx * g.nz + z) * 128 + 8 * j);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const float4 t = src[q];
-            v[2 * q] = cx<float>{t.x, t.y};
-            v[2 * q + 1] = cx<float>{t.z, t.w};
-        }
-    } else {
-        // S2[c][ky][kx][z] for ky = 8j + m
-#pragma unroll
-        for (int m = 0; m < 8; ++m) v[m] = Sin[cb + ((long long)(8 * j + m) * g.nh + kx) * g.nz + z];
-    }
-    // 16-point DIF over j: span h, lower lanes a + b, upper (a - b) w_2h^(j mod h)
-    auto stage = [&](auto hc) {
-        constexpr int H = decltype(hc)::value;
-        const bool up = (j & H) != 0;
-        const float sg = up ? -1.f : 1.f;
-        cx<float> w = {1.f, 0.f};
-        if (H > 1 && up) {
-            w = twy[(j & (H - 1)) * (64 / H)];  // w_2h^e = w_128^(64 e / h)
-            if (D > 0) w.y = -w.y;
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const float px = lane_xor<H>(v[m].x), py = lane_xor<H>(v[m].y);
-            cx<float> t = {px + sg * v[m].x, py + sg * v[m].y};
-            if constexpr (H > 1) t = cmul(t, w);
-            v[m] = t;
-        }
-    };
-    stage(std::integral_constant<int, 8>{});
-    stage(std::integral_constant<int, 4>{});
-    stage(std::integral_constant<int, 2>{});
-    stage(std::integral_constant<int, 1>{});
+    // per-lane twiddles: of the three span-h stages (upper lanes; 1 below)
+    // and w128^(m k2) of the lane's output index k2 = bitrev(j)
     const int k2 = (int)(__builtin_bitreverse32((unsigned)j) >> 28);
+    cx<float> ws[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int H = 8 >> s;
+        ws[s] = cx<float>{1.f, 0.f};
+        if (j & H) {
+            ws[s] = twy[(j & (H - 1)) * (64 / H)];  // w_2h^e = w_128^(64 e / h)
+            if (D > 0) ws[s].y = -ws[s].y;
+        }
+    }
+    cx<float> wm[8];
 #pragma unroll
     for (int m = 1; m < 8; ++m) {
-        cx<float> w = twy[(m * k2) & 127];
-        if (D > 0) w.y = -w.y;
-        v[m] = cmul(v[m], w);
+        wm[m] = twy[(m * k2) & 127];
+        if (D > 0) wm[m].y = -wm[m].y;
     }
-    dftR<float, 8, D>(v);
-    if constexpr (D < 0) {
-        // X[ky], ky = k2 + 16 k1, to S2[c][ky][kx][z]
+    // a task is four rows of a 16-row tile: rows 4 (t & 3) .. 4 (t & 3) + 3
+    // of tile t >> 2, one row per 16-lane group
+    auto row_of = [&](int t, int& kx, int& z, long long& cb) {
+        int b = t >> 2;
+        const int zt = b % nzt;
+        b /= nzt;
+        kx = b % g.nh;
+        cb = (long long)(b / g.nh) * g.nspec;
+        z = zt * 16 + 4 * (t & 3) + (lane >> 4);
+    };
+    cx<float> v[8];
+    auto load = [&](int t) {
+        int kx, z;
+        long long cb;
+        row_of(t, kx, z, cb);
+        if constexpr (D < 0) {
+            // row (c, kx, z) of S1, elements 8j .. 8j+7
+            const float4* src = reinterpret_cast<const float4*>(Sin + cb + ((long long)kx * g.nz + z) * 128 + 8 * j);
 #pragma unroll
-        for (int k1 = 0; k1 < 8; ++k1)
-            Sout[cb + ((long long)(k2 + 16 * k1) * g.nh + kx) * g.nz + z] = v[k1];
-    } else {
-        cx<float>* dst = Sout + cb + ((long long)kx * g.nz + z) * 128;
+            for (int q = 0; q < 4; ++q) {
+                const float4 u = src[q];
+                v[2 * q] = cx<float>{u.x, u.y};
+                v[2 * q + 1] = cx<float>{u.z, u.w};
+            }
+        } else {
+            // S2[c][ky][kx][z] for ky = 8j + m
 #pragma unroll
-        for (int k1 = 0; k1 < 8; ++k1) dst[k2 + 16 * k1] = v[k1];
+            for (int m = 0; m < 8; ++m) v[m] = Sin[cb + ((long long)(8 * j + m) * g.nh + kx) * g.nz + z];
+        }
+    };
+    const int gw = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int nw = gridDim.x * (kThreads / 64);
+    int t = gw;
+    if (t < ntasks) load(t);
+    for (; t < ntasks; t += nw) {
+        cx<float> a[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) a[m] = v[m];
+        if (t + nw < ntasks) load(t + nw);  // the next task's loads in flight
+        // 16-point DIF over j: span h, lower lanes a + b, upper (a - b) w_2h^(j mod h)
+        auto stage = [&](auto hc, const cx<float>& w) {
+            constexpr int H = decltype(hc)::value;
+            const float sg = (j & H) ? -1.f : 1.f;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const float px = lane_xor<H>(a[m].x), py = lane_xor<H>(a[m].y);
+                cx<float> u = {px + sg * a[m].x, py + sg * a[m].y};
+                if constexpr (H > 1) u = cmul(u, w);
+                a[m] = u;
+            }
+        };
+        stage(std::integral_constant<int, 8>{}, ws[0]);
+        stage(std::integral_constant<int, 4>{}, ws[1]);
+        stage(std::integral_constant<int, 2>{}, ws[2]);
+        stage(std::integral_constant<int, 1>{}, ws[2]);
+#pragma unroll
+        for (int m = 1; m < 8; ++m) a[m] = cmul(a[m], wm[m]);
+        dftR<float, 8, D>(a);
+        int kx, z;
+        long long cb;
+        row_of(t, kx, z, cb);
+        if constexpr (D < 0) {
+            // X[ky], ky = k2 + 16 k1, to S2[c][ky][kx][z]
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) Sout[cb + ((long long)(k2 + 16 * k1) * g.nh + kx) * g.nz + z] = a[k1];
+        } else {
+            cx<float>* dst = Sout + cb + ((long long)kx * g.nz + z) * 128;
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) dst[k2 + 16 * k1] = a[k1];
+        }
     }
 }
 

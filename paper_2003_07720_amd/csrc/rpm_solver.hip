@@ -492,12 +492,18 @@ struct Ctx {
     }
 };
 
-// y passes with register-resident transforms (rpm_tuning.y_regs; FP32 only)
+// y passes with register-resident transforms (rpm_tuning.y_regs; FP32 only):
+// a persistent grid of RPM_YWAVE_BLOCKS workgroups
+#ifndef RPM_YWAVE_BLOCKS
+#define RPM_YWAVE_BLOCKS 1024
+#endif
+constexpr int kYWaveBlocks = RPM_YWAVE_BLOCKS;
 template <typename T, int D>
 void launch_ywave(hipStream_t s, int tiles, const cx<T>* Sin, cx<T>* Sout, const Geo& g, const cx<T>* tw,
                   const int* done)
 {
-    if constexpr (sizeof(T) == 4) k_ywave<D><<<tiles, kThreads, 0, s>>>(Sin, Sout, g, tw, done);
+    if constexpr (sizeof(T) == 4)
+        k_ywave<D><<<std::min(tiles, kYWaveBlocks), kThreads, 0, s>>>(Sin, Sout, g, tw, 4 * tiles, done);
 }
 
 // One application of the fixed-point map on field xin (optionally corrected
