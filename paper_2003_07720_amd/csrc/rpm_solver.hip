@@ -72,7 +72,8 @@ constexpr bool kXInPlace = RPM_X_INPLACE != 0;  // in-place x transforms
 #define RPM_FUSE_RECOMBINE 1
 #endif
 // RPM recombination inside the x-forward pass (in-place 128-point x
-// transforms, not the polarization map)
+// transforms, not the polarization map; FP64 fields, or FP32 ones when the
+// split-column pass below is switched off)
 constexpr bool kFuseRecombine = RPM_FUSE_RECOMBINE != 0;
 #ifndef RPM_SPLIT_RECOMBINE
 #define RPM_SPLIT_RECOMBINE 1
