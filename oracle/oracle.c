@@ -18,7 +18,7 @@
  *     the paper names the operator in Sec. 2, eqs. for the periodic Green
  *     function, without printing it);
  *   - the Lippmann-Schwinger fixed-point map F of Algorithm 1 / Sec. 3 (the
- *     "formally define the fixed-point operator" equation): FFT of BOTH the
+ *     equation of Sec. 3 that defines the fixed-point operator): FFT of BOTH the
  *     strain and the stress (the literal 18-transform form), the update
  *     eps_hat - Gamma:sigma_hat at k != 0, the mean strain E at k = 0, the
  *     inverse FFT, and the equilibrium error of Algorithm 1;
