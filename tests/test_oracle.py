@@ -425,7 +425,7 @@ def test_seed_basis_complete_space_one_newton_step():
     np.testing.assert_allclose(r["eps"], ref_eps, atol=1e-12)
 
 
-# ------------------------------------------- prescribed mean stress (Sec. 2, "strain or stress")
+# ------------------------------------------- prescribed mean stress (Sec. 2: mean strain or mean stress given)
 
 def test_stress_control_homogeneous():
     """One phase: the strain is uniform, C^-1 Sigma (Mandel inverse), and <sigma> = Sigma."""
