@@ -36,9 +36,9 @@ KERNEL_SOURCES = ["include/rpmfft.h", "paper_2003_07720_amd/csrc/rpm_device.h",
 # kernel symbols behind each timing class of rpm_stats ({T}: float or double)
 CLASS_SYMBOLS = {
     "xfwd": r"rpm::k_xfwd<{T}, (true|false), false(, \d+)?(, (true|false)){0,3}>",
-    "yfwd": r"rpm::k_ypipe<{T}, -1, \d+(, (true|false))?>|rpm::k_yfwd<{T}>",
+    "yfwd": r"rpm::k_ypipe<{T}, -1, \d+(, (true|false))?>|rpm::k_yfwd<{T}>|rpm::k_ywave<-1>",
     "gamma": r"rpm::k_(gamma|gpipe)<{T}, false(, (true|false))?>",
-    "yinv": r"rpm::k_ypipe<{T}, 1, \d+(, (true|false))?>|rpm::k_yinv<{T}>",
+    "yinv": r"rpm::k_ypipe<{T}, 1, \d+(, (true|false))?>|rpm::k_yinv<{T}>|rpm::k_ywave<1>",
     "xinv": r"rpm::k_xinv<{T}, false(, \d+)?(, (true|false))?>",
     "project": r"rpm::k_gdots(_split)?<{T}, {T}, [12], 0(, \d+, \d+)?>",
     "recombine": r"rpm::k_recombine(_split)?<{T}(, \d+, \d+)?>",
